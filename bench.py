@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Throughput of the Fourier-kernel bilateral filter on one MI355X.
+
+One step = eq. (9) through Algorithm 1 (modulate, row and column smoothing,
+demodulate, accumulate, divide) over one batch of synthetic input that is
+already resident in HBM.  The default workload is 32 frames of 2160 x 3840
+(integer gray levels with smooth gradients), Gaussian spatial kernel
+sigma_s = 8 (W = 24), Gaussian range kernel sigma_r = 15, T = 255, K = 32,
+filtered in one batched call with 16-bit planes and float32 accumulation;
+the same batch is also timed with float32 planes for comparison.
+
+Prints ONE JSON line (rank 0).  Usage:
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision bf16|fp16|fp32]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpix/s, FP32 vs BF16-plane batched, at max err <0.5 gray level; % HBM peak"
+PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}   # dense MFMA, MI355X published
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def alg_flops_per_px(K, W):
+    """Separable smoothing of the 4K+1 planes: two passes of 2W+1 MACs each."""
+    return (4 * K + 1) * 2 * (2 * W + 1) * 2
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp32"])
+    ap.add_argument("--workload", default="frames32_2160x3840")
+    ap.add_argument("--frames", type=int, default=None, help="use only the first N frames")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the float32-plane comparison")
+    ap.add_argument("--no-check", action="store_true", help="skip the error check against the oracle")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the path shards by whole images or by "
+              "row stripes with W-row halos; no multi-GPU run is implemented); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1603_08081_amd as bfm  # noqa: F401
+    from paper_1603_08081_amd import native
+    from synth import WORKLOADS, workload_images
+
+    wl = WORKLOADS[args.workload]
+    if "height" not in wl:
+        raise SystemExit("bench.py times the single-kernel-setting workloads only")
+    t0 = time.time()
+    imgs = workload_images(args.workload, limit=args.frames)
+    n = len(imgs)
+    H, Wd = imgs[0].shape
+    log("generated %d x %dx%d in %.1fs" % (n, H, Wd, time.time() - t0))
+    dev = torch.device("cuda", 0)
+    src = torch.from_numpy(np.stack(imgs)).to(dev)
+    dst = torch.empty_like(src)
+    st, d, e2, em = native.bf_fit_coeffs(wl["range_kind"], wl["sigma_r"], wl["T"], wl["eps"], wl["K_max"])
+    K = len(d) - 1
+    W = wl["W"]
+
+    def make_jobs(prec_dst):
+        return [native.Job(src[i], prec_dst[i], spatial=wl["spatial"], sigma_s=wl["sigma_s"] or 1.0, W=W,
+                           range_kind=wl["range_kind"], sigma_r=wl["sigma_r"], T=wl["T"], d=d,
+                           integer_input=True) for i in range(n)]
+
+    stream = torch.cuda.current_stream()
+
+    def timed(prec, out, steps, warmup):
+        jobs = make_jobs(out)
+        ws_bytes = native.bf_workspace_bytes(jobs, prec)
+        ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+        for _ in range(warmup):
+            native.bf_filter_batched(jobs, prec, ws, ws_bytes, stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            native.bf_filter_batched(jobs, prec, ws, ws_bytes, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms = timed(args.precision, dst, args.steps, args.warmup)
+    px = n * H * Wd
+    value = px / (ms * 1e-3) / 1e6
+    log("%s planes: %.3f ms/step, %.1f Mpix/s" % (args.precision, ms, value))
+
+    extra = {}
+    if not args.no_fp32 and args.precision != "fp32":
+        dst32 = torch.empty_like(src)
+        ms32 = timed("fp32", dst32, max(2, args.steps // 4), 1)
+        v32 = px / (ms32 * 1e-3) / 1e6
+        log("fp32 planes: %.3f ms/step, %.1f Mpix/s" % (ms32, v32))
+        extra["fp32_value"] = round(v32, 1)
+        extra["fp32_ms_per_step"] = round(ms32, 3)
+        extra["speedup_vs_fp32"] = round(value / v32, 3)
+    else:
+        dst32 = dst if args.precision == "fp32" else None
+
+    # ---- roofline of the dominant kernel (one launch per frame in this path)
+    launches = n
+    avg_launch_s = ms * 1e-3 / launches
+    flops = alg_flops_per_px(K, W) * H * Wd
+    achieved = flops / avg_launch_s / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "kernel": "fused_kernel (modulate + row/column MFMA Toeplitz + demodulate)",
+            "alg_flops_per_px": alg_flops_per_px(K, W), "launches_per_step": launches}
+
+    # ---- error against the FP64 oracle (sampled rows of frame 0 and the last frame)
+    if not args.no_check:
+        import oracle
+        out16 = dst.cpu().numpy()
+        out32 = dst32.cpu().numpy() if dst32 is not None else None
+        rows = np.unique(np.array([0, 1, W - 1, W, H // 2, H - W - 1, H - 2, H - 1] +
+                                  list(np.random.default_rng(1).integers(0, H, 4))))
+        pix = (rows[:, None] * Wd + np.arange(Wd)[None, :]).ravel()
+        errs16, errs32, errsd = [], [], []
+        for fi in sorted({0, n - 1}):
+            ref = oracle.fourier(imgs[fi], wl["spatial"], wl["sigma_s"] or 1.0, W, d, wl["T"], pixels=pix)
+            dire = oracle.direct(imgs[fi], wl["spatial"], wl["sigma_s"] or 1.0, W, wl["range_kind"],
+                                 wl["sigma_r"], T=wl["T"], pixels=pix)
+            errs16.append(np.abs(out16[fi].ravel()[pix] - ref).max())
+            errsd.append(np.abs(out16[fi].ravel()[pix] - dire).max())
+            if out32 is not None:
+                errs32.append(np.abs(out32[fi].ravel()[pix] - ref).max())
+        extra["max_err_vs_fourier_fp64"] = float("%.4g" % max(errs16))
+        extra["max_err_vs_direct_fp64"] = float("%.4g" % max(errsd))
+        if errs32:
+            extra["fp32_max_err_vs_fourier_fp64"] = float("%.4g" % max(errs32))
+        extra["err_sample"] = "all pixels of %d rows of frames %s" % (len(rows), sorted({0, n - 1}))
+        extra["meets_0p5"] = bool(max(errs16) < 0.5)
+
+    # ---- CPU baseline: the FP64 oracle of eq. (9) on a bounded sample of frame 0
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        f0 = imgs[0]
+        oracle.fourier(f0, wl["spatial"], wl["sigma_s"] or 1.0, W, d, wl["T"],
+                       pixels=np.arange(Wd))  # warm (threads, page-in)
+        t1 = time.time()
+        oracle.fourier(f0, wl["spatial"], wl["sigma_s"] or 1.0, W, d, wl["T"], pixels=np.arange(2 * Wd))
+        per_row = (time.time() - t1) / 2
+        nrows = int(max(1, min(H, args.cpu_seconds / max(per_row, 1e-6))))
+        r0 = (H - nrows) // 2
+        pix = np.arange(r0 * Wd, (r0 + nrows) * Wd)
+        t1 = time.time()
+        oracle.fourier(f0, wl["spatial"], wl["sigma_s"] or 1.0, W, d, wl["T"], pixels=pix)
+        dt = time.time() - t1
+        cpu = {"value": round(pix.size / dt / 1e6, 4), "unit": "Mpix/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": "eq. (9) in FP64 on %d full rows (%d px) of frame 0, %.1f s" % (nrows, pix.size, dt)}
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "Mpix/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": args.workload, "frames": n, "height": H, "width": Wd,
+                   "spatial": wl["spatial"], "sigma_s": wl["sigma_s"], "W": W,
+                   "range": wl["range_kind"], "sigma_r": wl["sigma_r"], "T": wl["T"], "K": K,
+                   "planes": args.precision, "accumulation": "fp32"},
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

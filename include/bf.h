@@ -1,0 +1,175 @@
+/*
+ * bf.h -- C ABI of the MI355X (gfx950) Fourier-kernel bilateral filter.
+ *
+ * Method: Ghosh & Chaudhury, "On Fast Bilateral Filtering using Fourier
+ * Kernels".  The range kernel phi is fitted on {0..T} by the cosine series
+ * phi_K(t) = d_0 + sum_{k=1..K} d_k cos(k w t), w = pi / T (eq. (6)), with the
+ * progressive least-squares scheme of Algorithm 2 (Sec. 3); the filter then
+ * evaluates eq. (9) -- the bilateral filter of eq. (1) with phi replaced by
+ * phi_K -- through the shiftable decomposition of Algorithm 1 (Sec. 2): each
+ * harmonic k modulates the image into cos(k w f), sin(k w f), f cos(k w f) and
+ * f sin(k w f), smooths the four planes with the spatial kernel, demodulates
+ * at the output pixel with the conjugate phase and accumulates numerator and
+ * denominator, which are divided at the end.
+ *
+ * Conventions used by every entry point:
+ *   - All functions are extern "C"; no C++ exception crosses the ABI.
+ *   - Return value: BF_OK (0), a positive warning, or a negative error code.
+ *     On an error nothing has been enqueued and no output was written;
+ *     bf_last_error() returns a text for the calling thread.
+ *   - Images are row-major float32 gray levels with a row pitch counted in
+ *     elements (pitch >= width).  Pixel values are expected in [0, T]; the
+ *     accuracy guarantee of eq. (12) assumes that range.
+ *   - Device pointers (src, dst, workspace) are owned by the caller.  The
+ *     library never allocates, frees or synchronises caller memory or the
+ *     caller's stream; work is enqueued on `hip_stream` (a hipStream_t, NULL
+ *     for the null stream) and runs asynchronously.  Host arrays passed in
+ *     (phi_table, d) are read before the call returns.
+ *   - Borders use half-sample symmetric extension (f(-1) = f(0),
+ *     f(-2) = f(1), ...), which requires W < min(height, width).
+ *   - The spatial kernel is the Gaussian of eq. (2), exp(-(x^2+y^2)/(2 s^2)),
+ *     or a box (w = 1), on the window [-W, W]^2 (Sec. 1); it is scaled to unit
+ *     sum, which does not change eq. (1) or eq. (9).
+ */
+#ifndef BF_H
+#define BF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define BF_OK 0
+#define BF_FIT_NOT_CONVERGED 1  /* warning: the fit stopped at K_max with E > eps; outputs are valid */
+#define BF_E_INVALID (-1)       /* an argument violates the contract stated below */
+#define BF_E_DEVICE (-2)        /* a HIP runtime call failed (text in bf_last_error) */
+#define BF_E_WORKSPACE (-4)     /* workspace NULL or smaller than bf_workspace_bytes() */
+#define BF_E_UNSUPPORTED (-5)   /* valid for the method but beyond this library's limits */
+
+/* ---- limits of this implementation ------------------------------------- */
+#define BF_MAX_T 1024           /* half-period T (phase table of 2T entries per workgroup) */
+#define BF_MAX_K 255            /* harmonics usable by the filter (the fit accepts K_max <= T) */
+#define BF_MAX_W 64             /* window half-width */
+
+/* ---- enums -------------------------------------------------------------- */
+typedef enum {
+  BF_RANGE_GAUSSIAN = 0,     /* eq. (3): phi(t) = exp(-t^2 / (2 sigma_r^2)) */
+  BF_RANGE_EXPONENTIAL = 1,  /* phi(t) = exp(-|t| / sigma_r) */
+  BF_RANGE_TABLE = 2         /* phi given by its samples phi(0..T) (symmetric kernel) */
+} bf_range_kind;
+
+typedef enum {
+  BF_SPATIAL_GAUSSIAN = 0,   /* eq. (2) on [-W, W]^2 */
+  BF_SPATIAL_BOX = 1         /* w = 1 on [-W, W]^2 */
+} bf_spatial_kind;
+
+typedef enum {
+  BF_PLANES_FP32 = 0,        /* planes, smoothing and accumulation in float32 */
+  BF_PLANES_FP16 = 1,        /* planes and smoothing operands in float16 (RNE), float32 accumulation */
+  BF_PLANES_BF16 = 2         /* planes and smoothing operands in bfloat16 (RNE), float32 accumulation */
+} bf_planes;
+
+/* flags of bf_job.flags */
+#define BF_FLAG_INTEGER_INPUT 1 /* caller guarantees every pixel is an integer in [0, T]: enables
+                                   the exact table-only phase path.  With the flag set and a
+                                   non-integer pixel, that pixel's phase k*f is truncated to an
+                                   integer before reduction mod 2T. */
+
+/*
+ * bf_fit_coeffs -- Algorithm 2 (Sec. 3), on the host, in float64.
+ *
+ * Samples b = phi(0..T) (eq. (3), the exponential, or phi_table), then adds
+ * the columns cos(n w t), n = 0, 1, 2, ... one at a time, growing a thin QR
+ * factorisation by modified Gram-Schmidt and solving R d = Q^T b by
+ * back-substitution, until E = ||b - A d||_2 <= eps (eq. (7)/(8)) or the
+ * highest harmonic reaches K_max.  eps == 0 therefore gives exactly K_max
+ * harmonics.  (The column added when the fit has N columns is harmonic
+ * N - 1; the printed counts of Tables 3 and 4 are column counts K + 1.)
+ *
+ *   kind, sigma_r   range kernel; sigma_r > 0 unless kind == BF_RANGE_TABLE
+ *   phi_table       host array of T+1 samples phi(0..T); required iff TABLE
+ *   T               half-period, 1 <= T <= BF_MAX_T
+ *   eps             tolerance on ||b - A d||_2, eps >= 0
+ *   K_max           cap on the highest harmonic, 0 <= K_max <= T
+ *   d               host output, room for K_max + 1 doubles: d_0..d_K
+ *   K               host output: highest harmonic used
+ *   err_l2, err_max optional host outputs (may be NULL): ||b - A d||_2 and
+ *                   max_t |phi(t) - phi_K(t)| on {0..T} (eq. (10))
+ * Returns BF_OK, BF_FIT_NOT_CONVERGED (K == K_max and E > eps; d is the
+ * K_max fit), or BF_E_INVALID.  Host-only: needs no GPU.
+ */
+int bf_fit_coeffs(bf_range_kind kind, double sigma_r, const double* phi_table, int T,
+                  double eps, int K_max, double* d, int* K, double* err_l2, double* err_max);
+
+/*
+ * One filtering job (one image).  Fields:
+ *   src, dst        device pointers; dst must not overlap src
+ *   height, width   image size in pixels, >= 1
+ *   src_pitch, dst_pitch   row pitch in elements, >= width
+ *   spatial         BF_SPATIAL_GAUSSIAN or BF_SPATIAL_BOX
+ *   sigma_s         Gaussian spatial scale (> 0); ignored for the box
+ *   W               window half-width, 0 <= W <= BF_MAX_W and W < min(height, width);
+ *                   W < 0 with the Gaussian selects W = ceil(3 sigma_s) (Sec. 1)
+ *   range, sigma_r, phi_table, T, eps, K_max   as for bf_fit_coeffs
+ *   d, K            optional host coefficients d_0..d_K of phi_K; when d != NULL
+ *                   the fit is skipped and range/sigma_r/phi_table/eps/K_max are
+ *                   not used (T still sets w = pi / T)
+ *   flags           BF_FLAG_* bits
+ */
+typedef struct bf_job {
+  const float* src;
+  float* dst;
+  int height, width;
+  int src_pitch, dst_pitch;
+  bf_spatial_kind spatial;
+  double sigma_s;
+  int W;
+  bf_range_kind range;
+  double sigma_r;
+  const double* phi_table;
+  int T;
+  double eps;
+  int K_max;
+  const double* d;
+  int K;
+  int flags;
+} bf_job;
+
+/*
+ * bf_workspace_bytes -- device workspace needed by bf_filter (n_jobs == 1)
+ * or bf_filter_batched for these jobs and plane precision.  Returns 0 when
+ * none is needed and (size_t)-1 when the jobs are invalid.
+ */
+size_t bf_workspace_bytes(const bf_job* jobs, int n_jobs, bf_planes prec);
+
+/*
+ * bf_filter -- eq. (9) for one image via Algorithm 1, on the GPU.
+ * Fits the range kernel first unless job->d is given.  workspace may be
+ * NULL when bf_workspace_bytes() is 0.  Returns BF_OK, BF_FIT_NOT_CONVERGED
+ * (filter ran with K = K_max), BF_E_INVALID, BF_E_UNSUPPORTED,
+ * BF_E_WORKSPACE or BF_E_DEVICE.
+ */
+int bf_filter(const bf_job* job, bf_planes prec, void* workspace, size_t ws_bytes, void* hip_stream);
+
+/*
+ * bf_filter_batched -- eq. (9) for n_jobs independent images of any sizes,
+ * each with its own spatial window, range kernel and K, in one launch of a
+ * persistent kernel that pulls (image, tile) work items from a table.
+ * The table is built on the host (fits included) and copied into the
+ * workspace (asynchronously, from library-owned pinned memory).
+ * Returns the first error found, else BF_FIT_NOT_CONVERGED if any job's fit
+ * stopped at K_max, else BF_OK.
+ */
+int bf_filter_batched(const bf_job* jobs, int n_jobs, bf_planes prec,
+                      void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Thread-local text describing the last non-OK status of this thread. */
+const char* bf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BF_H */

@@ -1,0 +1,27 @@
+"""MI355X (gfx950) Fourier-kernel shiftable bilateral filter.
+
+The C ABI (include/bf.h, libbf.so) holds the whole path: the host-side
+coefficient fit and the HIP kernels.  ``native`` is a thin ctypes binding
+with the ABI's names; ``filter`` below is a convenience wrapper that
+allocates the output tensor with torch and calls ``bf_filter``.
+"""
+from __future__ import annotations
+
+
+def filter(img, *, spatial="gaussian", sigma_s=3.0, W=-1, range_kind="gaussian", sigma_r=30.0,
+           T=255, eps=1e-2, K_max=None, d=None, precision="fp32", integer_input=False, out=None,
+           stream=None):
+    """Filter one 2-D float32 CUDA tensor with eq. (9); returns (out, status)."""
+    import torch
+
+    from . import native
+    if img.dtype != torch.float32 or img.dim() != 2 or not img.is_cuda:
+        raise ValueError("expected a 2-D float32 tensor on the GPU")
+    if img.stride(-1) != 1:
+        raise ValueError("rows must be contiguous")
+    if out is None:
+        out = torch.empty_like(img, memory_format=torch.contiguous_format)
+    job = native.Job(img, out, spatial=spatial, sigma_s=sigma_s, W=W, range_kind=range_kind,
+                     sigma_r=sigma_r, T=T, eps=eps, K_max=K_max, d=d, integer_input=integer_input)
+    st = native.bf_filter(job, precision, stream=stream)
+    return out, st

@@ -1,0 +1,59 @@
+// Internal declarations shared by the host side of libbf (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/bf.h"
+
+namespace bf {
+
+// ---- host fit -------------------------------------------------------------
+struct FitOutcome {
+  int K = 0;
+  std::vector<double> d;
+  double err_l2 = 0.0;
+  double err_max = 0.0;
+  bool converged = false;
+};
+
+int sample_range_kernel(bf_range_kind kind, double sigma_r, const double* table, int T,
+                        std::vector<double>& b);
+FitOutcome fit_cosine_series(const std::vector<double>& b, int T, double eps, int K_max);
+
+// ---- device-side job description -------------------------------------------
+// Everything one image needs on the device.  Passed by value as a kernel
+// argument for bf_filter; stored in the workspace table for bf_filter_batched.
+struct JobDesc {
+  const float* src;
+  float* dst;
+  int height, width, src_pitch, dst_pitch;
+  int W;            // window half-width
+  int K;            // highest harmonic
+  int T;            // half-period
+  int flags;
+  float c0;         // range centring constant (T / 2)
+  float w1[2 * BF_MAX_W + 1];   // unit-sum 1-D spatial profile on [-W, W]
+  double d[BF_MAX_K + 1];       // coefficients d_0..d_K
+};
+
+// Geometry of the fused kernel: a workgroup of 4 waves owns a 64-column by
+// `th`-row output tile; one wave owns a 16-column strip of it.
+constexpr int kWaves = 4;
+constexpr int kTileCols = 16 * kWaves;
+
+// number of 16-row tiles spanned by 16 output rows plus a W-row halo on each side
+inline int window_tiles(int W) {
+  int nt = (16 + 2 * W + 15) / 16;
+  return nt < 2 ? 2 : nt;
+}
+
+// launchers (bf_kernels*.hip); return the hipError_t of the launch
+hipError_t launch_fused(const JobDesc& job, bf_planes prec, int th, hipStream_t stream);
+
+// thread-local error text
+void set_error(const std::string& msg);
+
+}  // namespace bf

@@ -1,0 +1,206 @@
+"""ctypes binding of libbf.so (include/bf.h), names as in the C ABI.
+
+This layer only marshals arguments: torch tensors provide device memory and
+streams, every step of the filter runs in the library's HIP kernels.  If the
+library is missing the import fails; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libbf.so")
+
+BF_OK = 0
+BF_FIT_NOT_CONVERGED = 1
+BF_E_INVALID = -1
+BF_E_DEVICE = -2
+BF_E_WORKSPACE = -4
+BF_E_UNSUPPORTED = -5
+BF_MAX_T = 1024
+BF_MAX_K = 255
+BF_MAX_W = 64
+
+RANGE = {"gaussian": 0, "exponential": 1, "table": 2}
+SPATIAL = {"gaussian": 0, "box": 1}
+PLANES = {"fp32": 0, "fp16": 1, "bf16": 2}
+BF_FLAG_INTEGER_INPUT = 1
+
+
+class BfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("libbf error %d: %s" % (code, msg))
+        self.code = code
+
+
+class bf_job(ctypes.Structure):
+    _fields_ = [
+        ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p),
+        ("height", ctypes.c_int), ("width", ctypes.c_int),
+        ("src_pitch", ctypes.c_int), ("dst_pitch", ctypes.c_int),
+        ("spatial", ctypes.c_int), ("sigma_s", ctypes.c_double), ("W", ctypes.c_int),
+        ("range", ctypes.c_int), ("sigma_r", ctypes.c_double),
+        ("phi_table", ctypes.POINTER(ctypes.c_double)),
+        ("T", ctypes.c_int), ("eps", ctypes.c_double), ("K_max", ctypes.c_int),
+        ("d", ctypes.POINTER(ctypes.c_double)), ("K", ctypes.c_int),
+        ("flags", ctypes.c_int),
+    ]
+
+
+def _hip_runtimes():
+    """Distinct HIP / HSA runtime files mapped into this process."""
+    try:
+        with open("/proc/self/maps") as fh:
+            paths = {ln.split()[-1] for ln in fh if "libamdhip64" in ln or "libhsa-runtime64" in ln}
+    except OSError:
+        return set()
+    return paths
+
+
+def _load():
+    # torch's wheel ships its own HIP runtime (same soname as /opt/rocm's).
+    # Importing torch first makes libbf bind to that copy, so the process
+    # holds one HIP runtime and torch's streams and pointers are valid here.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libbf.so is not built (run `python -m paper_1603_08081_amd.build`); "
+                          "there is no fallback path")
+    lib = ctypes.CDLL(LIB_PATH)
+    D, I, Z, P = ctypes.c_double, ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    jp = ctypes.POINTER(bf_job)
+    lib.bf_fit_coeffs.argtypes = [I, D, dp, I, D, I, dp, ip, dp, dp]
+    lib.bf_fit_coeffs.restype = I
+    lib.bf_workspace_bytes.argtypes = [jp, I, I]
+    lib.bf_workspace_bytes.restype = Z
+    lib.bf_filter.argtypes = [jp, I, P, Z, P]
+    lib.bf_filter.restype = I
+    lib.bf_filter_batched.argtypes = [jp, I, I, P, Z, P]
+    lib.bf_filter_batched.restype = I
+    lib.bf_last_error.argtypes = []
+    lib.bf_last_error.restype = ctypes.c_char_p
+    hip = sorted(p for p in _hip_runtimes() if "libamdhip64" in p)
+    if len(hip) > 1:
+        raise ImportError("two HIP runtimes are loaded (%s); import torch before anything that "
+                          "loads /opt/rocm's libamdhip64" % ", ".join(hip))
+    return lib
+
+
+lib = _load()
+
+
+def bf_last_error() -> str:
+    return lib.bf_last_error().decode()
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise BfError(rc, bf_last_error())
+    return rc
+
+
+def bf_fit_coeffs(kind: str, sigma_r: float, T: int, eps: float, K_max: int, phi_table=None):
+    """Algorithm 2 on the host.  Returns (status, d[0..K], err_l2, err_max)."""
+    tab = None
+    if phi_table is not None:
+        tab = np.ascontiguousarray(phi_table, dtype=np.float64)
+    d = np.zeros(max(K_max, 0) + 1, dtype=np.float64)
+    K = ctypes.c_int(-1)
+    e2 = ctypes.c_double(0.0)
+    em = ctypes.c_double(0.0)
+    rc = lib.bf_fit_coeffs(RANGE[kind], float(sigma_r),
+                           tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if tab is not None else None,
+                           int(T), float(eps), int(K_max), d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                           ctypes.byref(K), ctypes.byref(e2), ctypes.byref(em))
+    _check(rc)
+    return rc, d[:K.value + 1].copy(), e2.value, em.value
+
+
+class Job:
+    """Python-side holder of one bf_job (keeps host arrays alive)."""
+
+    def __init__(self, src, dst, *, spatial="gaussian", sigma_s=1.0, W=-1, range_kind="gaussian",
+                 sigma_r=30.0, T=255, eps=1e-2, K_max=None, d=None, phi_table=None,
+                 integer_input=False, height=None, width=None, src_pitch=None, dst_pitch=None):
+        self._keep = []
+        s = bf_job()
+        s.src = _ptr(src)
+        s.dst = _ptr(dst)
+        h, w = _hw(src) if height is None else (height, width)
+        s.height, s.width = int(h), int(w)
+        s.src_pitch = int(src_pitch if src_pitch is not None else _pitch(src, w))
+        s.dst_pitch = int(dst_pitch if dst_pitch is not None else _pitch(dst, w))
+        s.spatial = SPATIAL[spatial]
+        s.sigma_s = float(sigma_s)
+        s.W = int(W)
+        s.range = RANGE[range_kind]
+        s.sigma_r = float(sigma_r)
+        if phi_table is not None:
+            tab = np.ascontiguousarray(phi_table, dtype=np.float64)
+            self._keep.append(tab)
+            s.phi_table = tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        s.T = int(T)
+        s.eps = float(eps)
+        s.K_max = int(T if K_max is None else K_max)
+        if d is not None:
+            dd = np.ascontiguousarray(d, dtype=np.float64)
+            self._keep.append(dd)
+            s.d = dd.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            s.K = len(dd) - 1
+        s.flags = BF_FLAG_INTEGER_INPUT if integer_input else 0
+        self.struct = s
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return int(t.data_ptr())
+
+
+def _hw(t):
+    return int(t.shape[-2]), int(t.shape[-1])
+
+
+def _pitch(t, w):
+    if t is None or isinstance(t, int):
+        return w
+    return int(t.stride(-2))
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def bf_workspace_bytes(jobs: Sequence[Job], prec: str = "fp32") -> int:
+    arr = (bf_job * len(jobs))(*[j.struct for j in jobs])
+    n = lib.bf_workspace_bytes(arr, len(jobs), PLANES[prec])
+    if n == ctypes.c_size_t(-1).value:
+        raise BfError(BF_E_INVALID, bf_last_error())
+    return int(n)
+
+
+def bf_filter(job: Job, prec: str = "fp32", workspace=None, ws_bytes: int = 0, stream=None) -> int:
+    return _check(lib.bf_filter(ctypes.byref(job.struct), PLANES[prec], _ptr(workspace), int(ws_bytes),
+                                _stream_handle(stream)))
+
+
+def bf_filter_batched(jobs: Sequence[Job], prec: str = "fp32", workspace=None, ws_bytes: int = 0,
+                      stream=None) -> int:
+    arr = (bf_job * len(jobs))(*[j.struct for j in jobs])
+    return _check(lib.bf_filter_batched(arr, len(jobs), PLANES[prec], _ptr(workspace), int(ws_bytes),
+                                        _stream_handle(stream)))

@@ -1,0 +1,139 @@
+"""C-ABI checks that need no GPU: the library loads, exports what
+include/bf.h declares, its host fit agrees with the FP64 oracle, and every
+argument error is reported before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1603_08081_amd import native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE_SRC = 0x10000000   # never dereferenced: validation fails before any device call
+FAKE_DST = 0x20000000
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        txt = open(os.path.join(ROOT, "include", fn)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_ ]*\*?\s*\b(bf_[a-z_0-9]+)\s*\(", txt, re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert {"bf_fit_coeffs", "bf_filter", "bf_filter_batched", "bf_workspace_bytes", "bf_last_error"} <= names
+    lib = ctypes.CDLL(native.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+@pytest.mark.parametrize("kind,sigma,T,eps,kmax", [
+    ("gaussian", 30.0, 217, 1e-3, 217), ("gaussian", 30.0, 255, 1e-2, 255),
+    ("exponential", 20.0, 255, 1e-2, 24), ("gaussian", 10.0, 255, 0.0, 40),
+    ("gaussian", 15.0, 255, 0.0, 32), ("gaussian", 80.0, 255, 1e-5, 255)])
+def test_host_fit_matches_oracle(kind, sigma, T, eps, kmax):
+    st, d, e2, em = native.bf_fit_coeffs(kind, sigma, T, eps, kmax)
+    r = oracle.fit_kernel(kind, sigma, T, eps, kmax)
+    assert len(d) == r.K + 1
+    np.testing.assert_allclose(d, r.d, rtol=0, atol=1e-10)
+    assert abs(e2 - r.E) < 1e-10
+    em_ref = np.abs(oracle.series(r.d, T, np.arange(T + 1)) - r.b).max()
+    assert abs(em - em_ref) < 1e-10
+    assert st == (native.BF_OK if r.converged else native.BF_FIT_NOT_CONVERGED)
+
+
+def test_host_fit_table_kernel():
+    T = 100
+    t = np.arange(T + 1)
+    phi = 0.25 + 0.5 * np.cos(3 * np.pi * t / T) + 0.25 * np.cos(7 * np.pi * t / T)
+    st, d, e2, _ = native.bf_fit_coeffs("table", 0.0, T, 1e-12, T, phi_table=phi)
+    assert st == native.BF_OK and len(d) == 8 and e2 < 1e-12
+    np.testing.assert_allclose(d[[0, 3, 7]], [0.25, 0.5, 0.25], atol=1e-12)
+
+
+def test_tables_3_and_4_through_the_abi(golden_dir):
+    for line in open(os.path.join(golden_dir, "paper_table3_table4.txt")):
+        if line.strip() and not line.startswith("#"):
+            eps, n, _ = line.split()
+            st, d, _, _ = native.bf_fit_coeffs("gaussian", 30.0, 217, float(eps), 217)
+            assert st == native.BF_OK and len(d) == int(n)
+
+
+@pytest.mark.parametrize("args", [
+    ("gaussian", 30.0, 0, 1e-3, 0), ("gaussian", 30.0, 2000, 1e-3, 10),
+    ("gaussian", 30.0, 255, -1.0, 10), ("gaussian", 30.0, 255, 1e-3, 256),
+    ("gaussian", 0.0, 255, 1e-3, 10), ("exponential", -1.0, 255, 1e-3, 10),
+    ("table", 0.0, 255, 1e-3, 10)])
+def test_fit_rejects_bad_arguments(args):
+    with pytest.raises(native.BfError) as ei:
+        native.bf_fit_coeffs(*args)
+    assert ei.value.code == native.BF_E_INVALID
+    assert native.bf_last_error()
+
+
+def test_fit_cap_warns():
+    st, d, e2, _ = native.bf_fit_coeffs("exponential", 20.0, 255, 1e-2, 24)
+    assert st == native.BF_FIT_NOT_CONVERGED and len(d) == 25 and e2 > 1e-2
+
+
+def _job(**kw):
+    base = dict(spatial="gaussian", sigma_s=3.0, W=9, range_kind="gaussian", sigma_r=30.0, T=255,
+                eps=1e-2, K_max=40, height=64, width=64)
+    base.update(kw)
+    src = base.pop("src", FAKE_SRC)
+    dst = base.pop("dst", FAKE_DST)
+    return native.Job(src, dst, **base)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(src=None), native.BF_E_INVALID),
+    (dict(dst=None), native.BF_E_INVALID),
+    (dict(height=0), native.BF_E_INVALID),
+    (dict(width=-3), native.BF_E_INVALID),
+    (dict(src_pitch=10), native.BF_E_INVALID),
+    (dict(W=64, height=64), native.BF_E_INVALID),
+    (dict(W=9, width=9), native.BF_E_INVALID),
+    (dict(W=65, height=200, width=200), native.BF_E_UNSUPPORTED),
+    (dict(sigma_s=0.0), native.BF_E_INVALID),
+    (dict(spatial="box", W=-1), native.BF_E_INVALID),
+    (dict(W=-1, sigma_s=30.0, height=500, width=500), native.BF_E_UNSUPPORTED),
+    (dict(T=0), native.BF_E_INVALID),
+    (dict(T=4096), native.BF_E_INVALID),
+    (dict(K_max=300), native.BF_E_INVALID),
+    (dict(T=1000, K_max=300), native.BF_E_UNSUPPORTED),
+    (dict(sigma_r=-1.0), native.BF_E_INVALID),
+    (dict(range_kind="table"), native.BF_E_INVALID),
+    (dict(d=np.ones(300)), native.BF_E_UNSUPPORTED),
+    (dict(d=np.array([1.0, np.nan])), native.BF_E_INVALID),
+    (dict(dst=FAKE_SRC + 4 * 100), native.BF_E_INVALID),   # overlaps src
+])
+def test_filter_rejects_bad_jobs_before_device_work(kw, code):
+    j = _job(**kw)
+    with pytest.raises(native.BfError) as ei:
+        native.bf_filter(j, "fp32", stream=0)
+    assert ei.value.code == code
+    assert native.bf_last_error()
+    with pytest.raises(native.BfError):
+        native.bf_workspace_bytes([j])
+    with pytest.raises(native.BfError) as ei:
+        native.bf_filter_batched([_job(), j], "fp32", stream=0)
+    assert ei.value.code == code
+
+
+def test_unknown_precision_rejected():
+    rc = native.lib.bf_filter(ctypes.byref(_job().struct), 7, None, 0, None)
+    assert rc == native.BF_E_INVALID
+
+
+def test_workspace_query_for_valid_jobs():
+    assert native.bf_workspace_bytes([_job()], "fp32") >= 0
+    assert native.bf_workspace_bytes([_job(), _job(W=-1, sigma_s=2.0)], "fp16") >= 0

@@ -1,0 +1,194 @@
+"""GPU parity: bf_filter (through the C ABI) against the FP64 oracle.
+
+Bar (float32 planes): max |GPU - eq. (9) in FP64| <= 1e-3 gray levels at every
+compared pixel; where the kernel fit is tight, also < 0.5 against the direct
+filter of eq. (1).  16-bit planes: float16 must stay < 0.5 from eq. (9);
+bfloat16 errors are measured and bounded loosely (its 8-bit mantissa does not
+reach 0.5 on every workload).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import WORKLOADS, polygon_image, workload_images
+from tests.gpu_util import gpu_filter, pixels_of_rows, sample_rows
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-3
+
+
+def _fit(rk, sr, T=255, eps=1e-2, kmax=40):
+    return oracle.fit_kernel(rk, sr, T, eps, kmax)
+
+
+def _report(name, err):
+    print("%s: max err %.3e" % (name, err), flush=True)
+
+
+@pytest.mark.parametrize("shape", [(45, 77), (97, 131), (130, 67)])
+@pytest.mark.parametrize("spatial,W", [("gaussian", 1), ("gaussian", 5), ("gaussian", 9), ("box", 15),
+                                       ("gaussian", 24), ("gaussian", 30), ("box", 40)])
+@pytest.mark.parametrize("integer", [True, False])
+def test_fp32_ragged_shapes(shape, spatial, W, integer):
+    H, Wd = shape
+    if W >= min(H, Wd):
+        pytest.skip("window larger than image")
+    f = polygon_image(H, Wd, seed=H * 1000 + Wd + W)
+    sigma_s = max(W / 3.0, 0.5)
+    r = _fit("gaussian", 20.0, eps=1e-3)
+    out, st = gpu_filter(f, "fp32", spatial=spatial, sigma_s=sigma_s, W=W, T=255, d=r.d,
+                         integer_input=integer)
+    ref = oracle.fourier(f, spatial, sigma_s, W, r.d, 255)
+    err = np.abs(out - ref).max()
+    _report("ragged %s %s W=%d int=%s" % (shape, spatial, W, integer), err)
+    assert np.isfinite(out).all() and err <= TOL_FP32
+
+
+@pytest.mark.parametrize("W", [48, 56, 64])
+def test_fp32_widest_windows(W):
+    f = polygon_image(150, 141, seed=W)
+    r = _fit("gaussian", 30.0, eps=1e-3)
+    out, _ = gpu_filter(f, "fp32", spatial="gaussian", sigma_s=W / 3.0, W=W, T=255, d=r.d,
+                        integer_input=True)
+    ref = oracle.fourier(f, "gaussian", W / 3.0, W, r.d, 255)
+    err = np.abs(out - ref).max()
+    _report("wide W=%d" % W, err)
+    assert err <= TOL_FP32
+
+
+def test_gauss_256_full_image():
+    """256 x 256, Gaussian sigma_s = 3 (W = 9), Gaussian sigma_r = 30.
+
+    At the workload's eps = 1e-2 (K = 9) the GPU must match eq. (9) and stay
+    within the eq. (12) bound of the direct filter; at eps = 1e-5 the bound
+    itself is below half a gray level (the paper's sub-pixel guarantee), so
+    there the GPU must be < 0.5 from eq. (1) at every pixel."""
+    wl = WORKLOADS["gauss_256"]
+    f = workload_images("gauss_256")[0]
+    dire = oracle.direct(f, "gaussian", wl["sigma_s"], wl["W"], "gaussian", wl["sigma_r"])
+    w0 = oracle.center_weight("gaussian", wl["sigma_s"], wl["W"])
+    for eps, expect_k in ((wl["eps"], 9), (1e-5, None)):
+        r = _fit(wl["range_kind"], wl["sigma_r"], eps=eps, kmax=wl["K_max"])
+        if expect_k is not None:
+            assert r.K == expect_k
+        out, st = gpu_filter(f, "fp32", spatial="gaussian", sigma_s=wl["sigma_s"], W=wl["W"],
+                             range_kind=wl["range_kind"], sigma_r=wl["sigma_r"], T=255, eps=eps,
+                             K_max=wl["K_max"], integer_input=True)
+        assert st == 0
+        four = oracle.fourier(f, "gaussian", wl["sigma_s"], wl["W"], r.d, 255)
+        e1, e2 = np.abs(out - four).max(), np.abs(out - dire).max()
+        e_pt = np.abs(oracle.series(r.d, 255, np.arange(256)) - r.b).max()
+        bound = oracle.accuracy_bound(255, e_pt, w0)
+        _report("gauss_256 eps=%g K=%d vs fourier" % (eps, r.K), e1)
+        _report("gauss_256 eps=%g K=%d vs direct (eq. 12 bound %.3g)" % (eps, r.K, bound), e2)
+        assert e1 <= TOL_FP32
+        assert e2 <= bound + TOL_FP32
+        if bound < 0.5:
+            assert e2 < 0.5
+
+
+@pytest.mark.parametrize("name", ["exp_2048", "exp_2048_box"])
+def test_exp_2048_sampled_rows(name):
+    """2048^2, exponential sigma = 20 with K = 24 (fit capped), Gaussian W = 15
+    or box W = 15; all pixels of sampled rows against eq. (9)."""
+    wl = WORKLOADS[name]
+    f = workload_images(name)[0]
+    out, st = gpu_filter(f, "fp32", spatial=wl["spatial"], sigma_s=wl["sigma_s"] or 1.0, W=wl["W"],
+                         range_kind=wl["range_kind"], sigma_r=wl["sigma_r"], T=255, eps=wl["eps"],
+                         K_max=wl["K_max"], integer_input=True)
+    assert st == 1  # the exponential kernel does not reach eps = 1e-2 with K = 24
+    r = _fit(wl["range_kind"], wl["sigma_r"], eps=wl["eps"], kmax=wl["K_max"])
+    rows = sample_rows(*f.shape, W=wl["W"])
+    pix = pixels_of_rows(rows, f.shape[1])
+    ref = oracle.fourier(f, wl["spatial"], wl["sigma_s"] or 1.0, wl["W"], r.d, 255, pixels=pix)
+    err = np.abs(out.ravel()[pix] - ref).max()
+    _report(name + " vs fourier", err)
+    assert err <= TOL_FP32
+
+
+@pytest.mark.parametrize("name", ["gauss_8192", "frames32_2160x3840"])
+def test_large_sampled_rows(name):
+    wl = WORKLOADS[name]
+    f = workload_images(name, limit=1)[0]
+    out, st = gpu_filter(f, "fp32", spatial="gaussian", sigma_s=wl["sigma_s"], W=wl["W"],
+                         range_kind=wl["range_kind"], sigma_r=wl["sigma_r"], T=255, eps=wl["eps"],
+                         K_max=wl["K_max"], integer_input=True)
+    r = _fit(wl["range_kind"], wl["sigma_r"], eps=wl["eps"], kmax=wl["K_max"])
+    rows = sample_rows(*f.shape, W=wl["W"], n_random=8)
+    pix = pixels_of_rows(rows, f.shape[1])
+    ref = oracle.fourier(f, "gaussian", wl["sigma_s"], wl["W"], r.d, 255, pixels=pix)
+    dire = oracle.direct(f, "gaussian", wl["sigma_s"], wl["W"], wl["range_kind"], wl["sigma_r"], pixels=pix)
+    e1 = np.abs(out.ravel()[pix] - ref).max()
+    e2 = np.abs(out.ravel()[pix] - dire).max()
+    _report(name + " vs fourier", e1)
+    _report(name + " vs direct", e2)
+    assert e1 <= TOL_FP32 and e2 < 0.5
+
+
+@pytest.mark.parametrize("prec,bound", [("fp16", 0.5), ("bf16", 4.0)])
+@pytest.mark.parametrize("name,crop", [("gauss_256", None), ("gauss_8192", (256, 320)),
+                                       ("frames32_2160x3840", (270, 480))])
+def test_16bit_planes(prec, bound, name, crop):
+    wl = WORKLOADS[name]
+    f = workload_images(name, limit=1)[0]
+    if crop:
+        f = np.ascontiguousarray(f[:crop[0], :crop[1]])
+    r = _fit(wl["range_kind"], wl["sigma_r"], eps=wl["eps"], kmax=wl["K_max"])
+    out, _ = gpu_filter(f, prec, spatial="gaussian", sigma_s=wl["sigma_s"], W=wl["W"], T=255, d=r.d,
+                        integer_input=True)
+    ref = oracle.fourier(f, "gaussian", wl["sigma_s"], wl["W"], r.d, 255)
+    err = np.abs(out - ref).max()
+    _report("%s %s" % (name, prec), err)
+    assert err < bound
+
+
+def test_non_integer_image_general_phase():
+    rng = np.random.default_rng(5)
+    f = rng.uniform(0, 255, size=(70, 90)).astype(np.float32)
+    r = _fit("gaussian", 25.0, eps=1e-3)
+    out, _ = gpu_filter(f, "fp32", spatial="gaussian", sigma_s=2.0, W=6, T=255, d=r.d)
+    ref = oracle.fourier(f, "gaussian", 2.0, 6, r.d, 255)
+    err = np.abs(out - ref).max()
+    _report("non-integer", err)
+    assert err <= TOL_FP32
+
+
+def test_small_T_and_zero_order():
+    f = np.floor(polygon_image(40, 50, 3) / 17.0).astype(np.float32)  # values 0..15
+    r = oracle.fit_kernel("gaussian", 3.0, 15, 1e-6)
+    out, _ = gpu_filter(f, "fp32", spatial="gaussian", sigma_s=2.0, W=6, T=15, d=r.d, integer_input=True)
+    assert np.abs(out - oracle.fourier(f, "gaussian", 2.0, 6, r.d, 15)).max() <= TOL_FP32
+    # K = 0: phi_K is the constant d_0, eq. (9) is the plain spatial filter
+    out0, _ = gpu_filter(f, "fp32", spatial="box", W=3, T=15, d=np.array([0.7]), integer_input=True)
+    assert np.abs(out0 - oracle.fourier(f, "box", 1.0, 3, np.array([0.7]), 15)).max() <= TOL_FP32
+
+
+def test_pitched_image_and_determinism():
+    import torch
+
+    import paper_1603_08081_amd as bfm
+    f = polygon_image(100, 120, 8)
+    base = torch.zeros((100, 160), dtype=torch.float32, device="cuda")
+    base[:, :120] = torch.from_numpy(f).cuda()
+    view = base[:, :120]
+    outbuf = torch.full((100, 200), -7.0, device="cuda")
+    out = outbuf[:, 40:160]
+    r = _fit("gaussian", 20.0, eps=1e-3)
+    bfm.filter(view, spatial="gaussian", sigma_s=3.0, W=9, T=255, d=r.d, out=out, integer_input=True)
+    torch.cuda.synchronize()
+    o1 = outbuf.cpu().numpy()
+    assert (o1[:, :40] == -7.0).all() and (o1[:, 160:] == -7.0).all()
+    ref = oracle.fourier(f, "gaussian", 3.0, 9, r.d, 255)
+    assert np.abs(o1[:, 40:160] - ref).max() <= TOL_FP32
+    bfm.filter(view, spatial="gaussian", sigma_s=3.0, W=9, T=255, d=r.d, out=out, integer_input=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(outbuf.cpu().numpy(), o1)
+
+
+def test_constant_image_unchanged():
+    f = np.full((64, 80), 131.0, dtype=np.float32)
+    r = _fit("gaussian", 10.0, eps=1e-4)
+    for prec in ("fp32", "fp16", "bf16"):
+        out, _ = gpu_filter(f, prec, spatial="gaussian", sigma_s=4.0, W=12, T=255, d=r.d, integer_input=True)
+        assert np.abs(out - 131.0).max() <= (TOL_FP32 if prec == "fp32" else 0.05), prec
