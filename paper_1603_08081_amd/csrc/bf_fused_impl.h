@@ -3,33 +3,39 @@
 //
 // Computes eq. (9) of the paper through Algorithm 1 in its real (cos/sin)
 // form: with theta_k(j) = k w f(j), w = pi / T, and c0 = T / 2,
-//   P(i) = sum_k d_k [cos theta_k(i) * (w * C_k)(i) + sin theta_k(i) * (w * S_k)(i)]  (Q)
-//   with C_k = cos theta_k, S_k = sin theta_k for the denominator and
-//   C_k = (f - c0) cos theta_k, S_k = (f - c0) sin theta_k for the numerator;
-//   the k = 0 term is d_0 (w * (f - c0)) for P and d_0 sum(w) for Q, and the
-//   output is P / Q + c0.  Summing the harmonics +k and -k of eq. (4) with
+//   Q(i) = sum_k d_k [cos theta_k(i) (w * C_k)(i) + sin theta_k(i) (w * S_k)(i)]
+//   with C_k = cos theta_k, S_k = sin theta_k, and P(i) the same sum with
+//   C_k = (f - c0) cos theta_k, S_k = (f - c0) sin theta_k; the k = 0 term is
+//   d_0 (w * (f - c0)) for P and d_0 sum(w) for Q, and the output is
+//   P / Q + c0.  Summing the harmonics +k and -k of eq. (4) with
 //   c_{+-k} = d_k / 2 gives exactly this real form (relation after eq. (6)).
 //
-// Work decomposition.  A workgroup (4 waves) owns a 64-column x TH-row output
-// tile; wave w owns the 16-column strip [X0 + 16w, X0 + 16w + 16).  For each
-// harmonic k the workgroup walks down the tile in 16-row steps:
-//   1. modulate 16 input rows (the strip plus a W-column halo) into LDS --
-//      each input pixel is modulated once per step and shared by the 4 waves;
+// Work decomposition.  A workgroup of NW waves owns a (16 NW)-column x
+// TH-row output tile; wave w owns the 16-column strip [X0 + 16w, +16).
+// For integer gray levels the haloed image tile is staged once into LDS
+// (borders folded there), and for each harmonic k the workgroup first
+// tabulates, for every gray level f in 0..T, the modulation values
+// (cos, sin, (f - c0) cos, (f - c0) sin)(k w f) and the demodulation phase;
+// every later lookup is indexed by f, so no per-pixel phase arithmetic is
+// left.  The workgroup then walks down the tile in 16-row steps:
+//   1. modulate 16 input rows (all strips plus the halo) into LDS planes --
+//      each input pixel is modulated once per step and shared by the waves;
 //   2. row pass: one MFMA banded-Toeplitz product per 32 (16-bit) or 4
 //      (fp32) input columns, with the Toeplitz weights held in registers;
-//      the 16x16 fp32 result of each plane stays in registers (a ring of the
-//      last NT row tiles);
+//      the 16x16 result of each plane stays in registers (a ring of the last
+//      NT row tiles);
 //   3. column pass: once the ring spans 16 output rows plus the W-row halos,
 //      a second Toeplitz product runs straight from the ring registers (the
 //      MFMA output layout of the row pass is, up to a fixed permutation of the
 //      contraction index that the weights absorb, the input layout of the
 //      column pass), so row-filtered planes never touch LDS or HBM;
-//   4. demodulate at the 16x16 output pixels and accumulate P, Q in fp32
+//   4. demodulate at the 16x16 output pixels and accumulate P, Q in
 //      registers.
-// The phase e^{i theta} is read from a 2T-entry table of cos/sin(pi m / T)
-// built per workgroup in float64 and rounded once; for integer gray levels
-// the index k f mod 2T is exact.
+// Non-integer images take a general path that computes the phase per pixel
+// (the integer part of k f through the cos/sin table of pi m / T, the
+// fractional part by an explicit rotation).
 #include <hip/hip_runtime.h>
+#include <stdint.h>
 
 #include <type_traits>
 
@@ -60,6 +66,9 @@ struct Planes<BF_PLANES_FP16> {
   using V8 = f16x8;
   using V4 = f16x4;
   static __device__ __forceinline__ float round(float x) { return (float)(_Float16)x; }
+  static __device__ __forceinline__ uint32_t bits(float x) {
+    return __builtin_bit_cast(uint16_t, (_Float16)x);
+  }
   static __device__ __forceinline__ f32x4 mma(V8 a, V8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }
@@ -71,10 +80,45 @@ struct Planes<BF_PLANES_BF16> {
   using V8 = b16x8;
   using V4 = b16x4;
   static __device__ __forceinline__ float round(float x) { return (float)(__bf16)x; }
+  static __device__ __forceinline__ uint32_t bits(float x) {
+    return __builtin_bit_cast(uint16_t, (__bf16)x);
+  }
   static __device__ __forceinline__ f32x4 mma(V8 a, V8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
 };
+
+// Tile geometry shared by the kernel and its launcher.
+template <int PREC, int NT>
+struct Geo {
+  static constexpr bool F32 = (PREC == BF_PLANES_FP32);
+  static constexpr int NW = F32 ? 4 : 8;                  // waves per workgroup
+  static constexpr int THREADS = 64 * NW;
+  static constexpr int COLS = 16 * NW;                    // output columns per workgroup
+  static constexpr int KS = (NT + 1) / 2;                 // 32-column contraction steps
+  static constexpr int LWU = 16 * (NW - 1) + 32 * KS;     // staged input columns
+  static constexpr int LW = F32 ? LWU + 4 : LWU + 8;      // padded plane row (elements)
+  static constexpr int FW = LWU + 8;                      // padded image-tile row (u16)
+};
+
+constexpr int kTabBytes = 16;  // one table entry per gray level
+constexpr size_t kLdsLimit = 160 * 1024;
+
+template <int PREC>
+constexpr int kThreadsFor = (PREC == BF_PLANES_FP32) ? 256 : 512;
+
+// static LDS of one instantiation, and whether its staged image tile fits
+template <int PREC, int NT, int TH, bool INTEGER>
+struct Lds {
+  using G = Geo<PREC, NT>;
+  static constexpr size_t planes = 2ull * 4 * 16 * G::LW * (G::F32 ? 4 : 2);
+  static constexpr size_t tile = INTEGER ? 2ull * 16 * (TH / 16 + NT - 1) * G::FW : 16;
+  static constexpr size_t total = planes + tile + 4 * (2 * BF_MAX_W + 1) + 64;
+  // a staged variant must leave room for at least the T = 255 tables
+  static constexpr bool fits = total + kTabBytes * 256 + 8 * 510 <= kLdsLimit;
+};
+
+inline size_t dynamic_lds(int T) { return (size_t)kTabBytes * (T + 1) + sizeof(float2) * 2 * (size_t)T; }
 
 template <int I, int N, typename F>
 __device__ __forceinline__ void static_for(F&& f) {
@@ -95,100 +139,109 @@ __device__ __forceinline__ int fold(int i, int n) {
 __device__ __forceinline__ float fma_acc(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ double fma_acc(double a, double b, double c) { return fma(a, b, c); }
 
+// m -> (cos, sin)(pi m / T), m = 0..2T-1, for the general (non-integer) path
 struct PhaseTab {
-  const float2* lut;  // cos, sin of pi m / T, m = 0..2T-1
+  const float2* lut;
   float two_t, inv_two_t, inv_t;
-  int n_lut;          // 2T
+  int n_lut;  // 2T
 };
 
-// cos and sin of k w f with w = pi / T
-template <bool INTEGER>
-__device__ __forceinline__ void phase(float kf, float f, const PhaseTab& pt, float& c, float& s) {
-  if constexpr (INTEGER) {
-    const float p = kf * f;  // exact for integer f
-    const float q = floorf(p * pt.inv_two_t);
-    float m = fmaf(-pt.two_t, q, p);
-    m = (m >= pt.two_t) ? m - pt.two_t : m;
-    m = (m < 0.f) ? m + pt.two_t : m;
-    const float2 v = pt.lut[min(max((int)m, 0), pt.n_lut - 1)];  // clamp: non-finite input
-    c = v.x;
-    s = v.y;
-  } else {
-    // k f = k floor(f) + k frac(f): the integer part indexes the table
-    // exactly, the remaining fraction r in [0, 1) is applied as a rotation
-    const float fi = floorf(f);
-    const float pf = kf * (f - fi);
-    const float n2 = floorf(pf);
-    const float r = pf - n2;
-    const float p = fmaf(kf, fi, n2);
-    const float q = floorf(p * pt.inv_two_t);
-    float m = fmaf(-pt.two_t, q, p);
-    m = (m >= pt.two_t) ? m - pt.two_t : m;
-    m = (m < 0.f) ? m + pt.two_t : m;
-    const float2 v = pt.lut[min(max((int)m, 0), pt.n_lut - 1)];
-    float sr, cr;
-    sincospif(r * pt.inv_t, &sr, &cr);
-    c = v.x * cr - v.y * sr;
-    s = v.y * cr + v.x * sr;
-  }
+__device__ __forceinline__ float reduce_2t(float p, const PhaseTab& pt) {
+  const float q = floorf(p * pt.inv_two_t);
+  float m = fmaf(-pt.two_t, q, p);
+  m = (m >= pt.two_t) ? m - pt.two_t : m;
+  return (m < 0.f) ? m + pt.two_t : m;
 }
 
-template <int PREC, int NT, int TH, bool INTEGER>
-__global__ void __launch_bounds__(256) fused_kernel(const JobDesc job) {
+// cos and sin of k w f, any real f: k f = k floor(f) + k frac(f); the integer
+// part indexes the table exactly, the remaining fraction r in [0, 1) is
+// applied as a rotation by pi r / T
+__device__ __forceinline__ void phase_general(float kf, float f, const PhaseTab& pt, float& c, float& s) {
+  const float fi = floorf(f);
+  const float pf = kf * (f - fi);
+  const float n2 = floorf(pf);
+  const float r = pf - n2;
+  const float m = reduce_2t(fmaf(kf, fi, n2), pt);
+  const float2 v = pt.lut[min(max((int)m, 0), pt.n_lut - 1)];  // clamp: non-finite input
+  float sr, cr;
+  sincospif(r * pt.inv_t, &sr, &cr);
+  c = v.x * cr - v.y * sr;
+  s = v.y * cr + v.x * sr;
+}
+
+template <int PREC, int NT, int TH, bool INTEGER_REQ>
+__global__ void __launch_bounds__(kThreadsFor<PREC>) fused_kernel(const JobDesc job) {
+  constexpr bool INTEGER = INTEGER_REQ && Lds<PREC, NT, TH, true>::fits;
+  using G = Geo<PREC, NT>;
   using PT = Planes<PREC>;
   using E = typename PT::E;
-  constexpr bool F32 = (PREC == BF_PLANES_FP32);
-  constexpr int KS = (NT + 1) / 2;       // 32-column contraction steps
-  constexpr int LWU = 48 + 32 * KS;      // LDS columns used per plane row
-  constexpr int LW = F32 ? LWU + 4 : LWU + 8;  // padded row (bank spread, 16 B aligned)
+  constexpr bool F32 = G::F32;
+  constexpr int NTHR = G::THREADS, KS = G::KS, LWU = G::LWU, LW = G::LW, FW = G::FW;
   constexpr int NJ = TH / 16;            // output row tiles per workgroup
   constexpr int NS = NJ + NT - 1;        // 16-row steps per harmonic
+  constexpr int FROWS = 16 * NS;         // staged image rows
 
   __shared__ __attribute__((aligned(16))) E planes[2][4][16][LW];
+  // image tile, stored as f * kTabBytes (byte offset of gray level f in the table)
+  __shared__ __attribute__((aligned(16))) uint16_t ftile[INTEGER ? FROWS : 1][INTEGER ? FW : 8];
   __shared__ float w1s[2 * BF_MAX_W + 1];
-  extern __shared__ float2 lut[];
+  // dynamic: per-harmonic table [(T+1) x 16 B], then cos/sin(pi m / T) [2T x 8 B]
+  extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, g = lane >> 4, n16 = lane & 15;
-  const int X0 = blockIdx.x * kTileCols, Y0 = blockIdx.y * TH;
+  const int X0 = blockIdx.x * G::COLS, Y0 = blockIdx.y * TH;
   const int x0 = X0 + 16 * wave;
   const int W = job.W, T = job.T, K = job.K;
+  const int Wal = (W + 7) & ~7;          // column origin of the staged tile: X0 - Wal
   const int H = job.height, Wd = job.width;
   const float* __restrict__ src = job.src;
   const int sp = job.src_pitch;
   const float c0 = job.c0;
+  unsigned char* tab = dyn;
+  float2* lut = reinterpret_cast<float2*>(dyn + (size_t)kTabBytes * (T + 1));
 
-  for (int m = tid; m < 2 * T; m += 256) {
+  for (int m = tid; m < 2 * T; m += NTHR) {
     double s, c;
     sincospi((double)m / (double)T, &s, &c);
     lut[m] = make_float2((float)c, (float)s);
   }
-  for (int t = tid; t <= 2 * W; t += 256) w1s[t] = job.w1[t];
+  for (int t = tid; t <= 2 * W; t += NTHR) w1s[t] = job.w1[t];
+  if constexpr (INTEGER) {
+    for (int idx = tid; idx < FROWS * LWU; idx += NTHR) {
+      const int r = idx / LWU, c = idx - r * LWU;
+      float v = src[(size_t)fold(Y0 - W + r, H) * sp + fold(X0 - Wal + c, Wd)];
+      v = fminf(fmaxf(v, 0.f), (float)T);  // NaN -> 0; the flag promises integers in [0, T]
+      ftile[r][c] = (uint16_t)((int)v * kTabBytes);
+    }
+  }
   __syncthreads();
 
   auto wq = [&](int dd) -> float { return (dd >= -W && dd <= W) ? PT::round(w1s[dd + W]) : 0.f; };
 
-  // Toeplitz operands.  Row pass: B[k][n] = w(input col - output col) with the
-  // input col of contraction slot k counted from x0 - W.  Column pass: the
+  // Toeplitz operands.  Row pass: B[k][n] = w(input col - output col), the
+  // input col of contraction slot k counted from x0 - Wal.  Column pass: the
   // contraction slot (lane group g, element e) holds row 4g + (e & 3) of ring
-  // tile 2ks + (e >> 2) (16-bit) or row 4g + i of ring tile t (fp32).
+  // tile 2ks + (e >> 2) (16-bit) or row 4g + i of ring tile t (fp32), rows
+  // counted from the output row - W.
   using BrowT = std::conditional_t<F32, float, typename std::conditional_t<F32, Planes<BF_PLANES_FP16>, PT>::V8>;
   constexpr int NBR = F32 ? 8 * KS : KS;
   BrowT brow[NBR];
   float bcol32[F32 ? NT : 1][4];
   BrowT bcol16[F32 ? 1 : KS];
   if constexpr (F32) {
-    for (int s4 = 0; s4 < NBR; ++s4) brow[s4] = wq(4 * s4 + g - W - n16);
+    for (int s4 = 0; s4 < NBR; ++s4) brow[s4] = wq(4 * s4 + g - Wal - n16);
     for (int t = 0; t < NT; ++t)
       for (int i = 0; i < 4; ++i) bcol32[t][i] = wq(16 * t + 4 * g + i - W - n16);
   } else {
     for (int ks = 0; ks < KS; ++ks)
       for (int e = 0; e < 8; ++e) {
-        brow[ks][e] = (E)wq(32 * ks + 8 * g + e - W - n16);
+        brow[ks][e] = (E)wq(32 * ks + 8 * g + e - Wal - n16);
         bcol16[ks][e] = (E)wq(16 * (2 * ks + (e >> 2)) + 4 * g + (e & 3) - W - n16);
       }
   }
-  const int nks4 = (16 + 2 * W + 3) / 4;  // fp32 row-pass steps with nonzero weights
+  // fp32 row-pass steps holding nonzero weights: columns [Wal - W, Wal + 16 + W)
+  const int s4lo = (Wal - W) / 4, s4hi = (Wal + 16 + W + 3) / 4;
   // fp32 planes accumulate P and Q in float64 (see the column pass below);
   // 16-bit planes are limited by their own rounding and accumulate in float32
   using Acc = std::conditional_t<F32, double, float>;
@@ -196,62 +249,120 @@ __global__ void __launch_bounds__(256) fused_kernel(const JobDesc job) {
   for (int t = -W; t <= W; ++t) wsum += (double)wq(t);
   const Acc q0 = (Acc)(job.d[0] * wsum * wsum);
 
-  // gray levels at this lane's output pixels: row Y0 + 16 j + n16, cols x0 + 4 g + i
-  float fo[NJ][4];
-  for (int j = 0; j < NJ; ++j)
-    for (int i = 0; i < 4; ++i) {
-      const int yy = min(Y0 + 16 * j + n16, H - 1), xx = min(x0 + 4 * g + i, Wd - 1);
-      fo[j][i] = src[(size_t)yy * sp + xx];
-    }
+  // general path: gray levels at this lane's output pixels (row Y0 + 16 j + n16, cols x0 + 4 g + i)
+  float fo[INTEGER ? 1 : NJ][4];
+  if constexpr (!INTEGER) {
+    for (int j = 0; j < NJ; ++j)
+      for (int i = 0; i < 4; ++i) {
+        const int yy = min(Y0 + 16 * j + n16, H - 1), xx = min(x0 + 4 * g + i, Wd - 1);
+        fo[j][i] = src[(size_t)yy * sp + xx];
+      }
+  }
   Acc P[NJ][4], Q[NJ][4];
   for (int j = 0; j < NJ; ++j)
     for (int i = 0; i < 4; ++i) P[j][i] = Q[j][i] = (Acc)0;
 
   const PhaseTab pt{lut, 2.f * (float)T, 1.f / (2.f * (float)T), 1.f / (float)T, 2 * T};
+  const float two_t = 2.f * (float)T, inv_two_t = 1.f / (2.f * (float)T);
 
   using RingT = std::conditional_t<F32, f32x4, typename std::conditional_t<F32, Planes<BF_PLANES_FP16>, PT>::V4>;
 
   for (int k = 0; k <= K; ++k) {
     const float kf = (float)k;
     const Acc dk = (Acc)job.d[k];
+    __syncthreads();  // every wave is done with harmonic k - 1 (table and planes)
+    if constexpr (INTEGER) {
+      // per-harmonic table, entry f: fp32 (c, s, (f-c0) c, (f-c0) s) for fp32
+      // planes; for 16-bit planes (d_k c, d_k s) in fp32 for the demodulation
+      // and (c, s, (f-c0) c, (f-c0) s) rounded to the plane format
+      for (int f = tid; f <= T; f += NTHR) {
+        const float m = reduce_2t((float)k * (float)f, pt);
+        const float2 cs = lut[min(max((int)m, 0), 2 * T - 1)];
+        const float v = (float)f - c0;
+        unsigned char* ent = tab + (size_t)kTabBytes * f;
+        if constexpr (F32) {
+          *reinterpret_cast<float4*>(ent) = make_float4(cs.x, cs.y, v * cs.x, v * cs.y);
+        } else {
+          const float dkf = (float)job.d[k];
+          const uint32_t w0 = PT::bits(cs.x) | (PT::bits(cs.y) << 16);
+          const uint32_t w1 = PT::bits(v * cs.x) | (PT::bits(v * cs.y) << 16);
+          *reinterpret_cast<uint4*>(ent) =
+              make_uint4(__float_as_uint(dkf * cs.x), __float_as_uint(dkf * cs.y), w0, w1);
+        }
+      }
+      __syncthreads();
+    }
     auto run = [&](auto nplc) {
       constexpr int NPL = decltype(nplc)::value;  // 1 for k = 0 (plane f - c0 only), else 4
       RingT ring[NT][NPL];
       static_for<0, NS>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
         constexpr int b = s & 1;
-        const int ybase = Y0 - W + 16 * s;
-        // ---- 1. modulate 16 rows into LDS buffer b
-        constexpr int CW = F32 ? 4 : 8;  // pixels per thread chunk
-        constexpr int CPR = LWU / CW;
-        for (int c = tid; c < 16 * CPR; c += 256) {
+        // ---- 1. modulate rows [16 s, 16 s + 16) of the tile into LDS buffer b
+        constexpr int CPR = LWU / 8;  // 8-pixel chunks per row
+        for (int c = tid; c < 16 * CPR; c += NTHR) {
           const int r = c / CPR, cc = c - r * CPR;
-          const float* rowp = src + (size_t)fold(ybase + r, H) * sp;
-          const int gx = X0 - W + CW * cc;
-          float fv[CW];
+          if constexpr (INTEGER) {
+            const uint4 fq = *reinterpret_cast<const uint4*>(&ftile[16 * s + r][8 * cc]);
+            const uint32_t fw[4] = {fq.x, fq.y, fq.z, fq.w};
+            if constexpr (F32) {
+              float pc[8], ps[8], pfc[8], pfs[8];
 #pragma unroll
-          for (int e = 0; e < CW; ++e) fv[e] = rowp[fold(gx + e, Wd)];
-          E vc[CW], vs[CW], vfc[CW], vfs[CW];
-#pragma unroll
-          for (int e = 0; e < CW; ++e) {
-            const float v = fv[e] - c0;
-            if constexpr (NPL == 4) {
-              float cs, sn;
-              phase<INTEGER>(kf, fv[e], pt, cs, sn);
-              vc[e] = (E)cs;
-              vs[e] = (E)sn;
-              vfc[e] = (E)(v * cs);
-              vfs[e] = (E)(v * sn);
+              for (int e = 0; e < 8; ++e) {
+                const uint32_t off = (e & 1) ? (fw[e >> 1] >> 16) : (fw[e >> 1] & 0xffffu);
+                const float4 t = *reinterpret_cast<const float4*>(tab + off);
+                pc[e] = t.x; ps[e] = t.y; pfc[e] = t.z; pfs[e] = t.w;
+              }
+              if constexpr (NPL == 4) {
+                __builtin_memcpy(&planes[b][0][r][8 * cc], pc, sizeof(pc));
+                __builtin_memcpy(&planes[b][1][r][8 * cc], ps, sizeof(ps));
+                __builtin_memcpy(&planes[b][3][r][8 * cc], pfs, sizeof(pfs));
+              }
+              __builtin_memcpy(&planes[b][2][r][8 * cc], pfc, sizeof(pfc));
             } else {
-              vfc[e] = (E)v;
+              uint32_t pc[4], ps[4], pfc[4], pfs[4];
+#pragma unroll
+              for (int h = 0; h < 4; ++h) {  // pixels 2h, 2h + 1
+                const uint2 ta = *reinterpret_cast<const uint2*>(tab + (fw[h] & 0xffffu) + 8);
+                const uint2 tb = *reinterpret_cast<const uint2*>(tab + (fw[h] >> 16) + 8);
+                pc[h] = (ta.x & 0xffffu) | (tb.x << 16);
+                ps[h] = (ta.x >> 16) | (tb.x & 0xffff0000u);
+                pfc[h] = (ta.y & 0xffffu) | (tb.y << 16);
+                pfs[h] = (ta.y >> 16) | (tb.y & 0xffff0000u);
+              }
+              if constexpr (NPL == 4) {
+                __builtin_memcpy(&planes[b][0][r][8 * cc], pc, sizeof(pc));
+                __builtin_memcpy(&planes[b][1][r][8 * cc], ps, sizeof(ps));
+                __builtin_memcpy(&planes[b][3][r][8 * cc], pfs, sizeof(pfs));
+              }
+              __builtin_memcpy(&planes[b][2][r][8 * cc], pfc, sizeof(pfc));
             }
+          } else {
+            const float* rowp = src + (size_t)fold(Y0 - W + 16 * s + r, H) * sp;
+            const int gx = X0 - Wal + 8 * cc;
+            E vc[8], vs[8], vfc[8], vfs[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const float fv = rowp[fold(gx + e, Wd)];
+              const float v = fv - c0;
+              if constexpr (NPL == 4) {
+                float cs, sn;
+                phase_general(kf, fv, pt, cs, sn);
+                vc[e] = (E)cs;
+                vs[e] = (E)sn;
+                vfc[e] = (E)(v * cs);
+                vfs[e] = (E)(v * sn);
+              } else {
+                vfc[e] = (E)v;
+              }
+            }
+            if constexpr (NPL == 4) {
+              __builtin_memcpy(&planes[b][0][r][8 * cc], vc, sizeof(vc));
+              __builtin_memcpy(&planes[b][1][r][8 * cc], vs, sizeof(vs));
+              __builtin_memcpy(&planes[b][3][r][8 * cc], vfs, sizeof(vfs));
+            }
+            __builtin_memcpy(&planes[b][2][r][8 * cc], vfc, sizeof(vfc));
           }
-          if constexpr (NPL == 4) {
-            __builtin_memcpy(&planes[b][0][r][CW * cc], vc, sizeof(vc));
-            __builtin_memcpy(&planes[b][1][r][CW * cc], vs, sizeof(vs));
-            __builtin_memcpy(&planes[b][3][r][CW * cc], vfs, sizeof(vfs));
-          }
-          __builtin_memcpy(&planes[b][2][r][CW * cc], vfc, sizeof(vfc));
         }
         __syncthreads();
         // ---- 2. row pass for this wave's strip
@@ -262,7 +373,7 @@ __global__ void __launch_bounds__(256) fused_kernel(const JobDesc job) {
           if constexpr (F32) {
 #pragma unroll
             for (int s4 = 0; s4 < NBR; ++s4)
-              if (s4 < nks4)
+              if (s4 >= s4lo && s4 < s4hi)
                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(planes[b][p][n16][16 * wave + 4 * s4 + g],
                                                             brow[s4], acc, 0, 0, 0);
             ring[s % NT][pi] = acc;
@@ -314,14 +425,38 @@ __global__ void __launch_bounds__(256) fused_kernel(const JobDesc job) {
               for (int i = 0; i < 4; ++i) fb[pi][i] = acc[i];
             }
           }
+          // demodulation phase at pixels (Y0 + 16 j + n16, x0 + 4 g + i)
+          Acc dcs[4], dsn[4];
+          if constexpr (NPL == 4) {
+            if constexpr (INTEGER) {
+              const uint2 fq = *reinterpret_cast<const uint2*>(&ftile[W + 16 * j + n16][Wal + 16 * wave + 4 * g]);
+              const uint32_t off[4] = {fq.x & 0xffffu, fq.x >> 16, fq.y & 0xffffu, fq.y >> 16};
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const float2 t = *reinterpret_cast<const float2*>(tab + off[i]);
+                if constexpr (F32) {
+                  dcs[i] = dk * (Acc)t.x;
+                  dsn[i] = dk * (Acc)t.y;
+                } else {
+                  dcs[i] = t.x;  // the 16-bit table already holds d_k cos, d_k sin
+                  dsn[i] = t.y;
+                }
+              }
+            } else {
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                float cs, sn;
+                phase_general(kf, fo[j][i], pt, cs, sn);
+                dcs[i] = dk * (Acc)cs;
+                dsn[i] = dk * (Acc)sn;
+              }
+            }
+          }
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             if constexpr (NPL == 4) {
-              float cs, sn;
-              phase<INTEGER>(kf, fo[j][i], pt, cs, sn);
-              const Acc dc = dk * (Acc)cs, ds = dk * (Acc)sn;
-              P[j][i] = fma_acc(dc, fb[2][i], fma_acc(ds, fb[3][i], P[j][i]));
-              Q[j][i] = fma_acc(dc, fb[0][i], fma_acc(ds, fb[1][i], Q[j][i]));
+              P[j][i] = fma_acc(dcs[i], fb[2][i], fma_acc(dsn[i], fb[3][i], P[j][i]));
+              Q[j][i] = fma_acc(dcs[i], fb[0][i], fma_acc(dsn[i], fb[1][i], Q[j][i]));
             } else {
               P[j][i] = fma_acc(dk, fb[0][i], P[j][i]);
               Q[j][i] += q0;
@@ -332,7 +467,6 @@ __global__ void __launch_bounds__(256) fused_kernel(const JobDesc job) {
     };
     if (k == 0) run(std::integral_constant<int, 1>{});
     else run(std::integral_constant<int, 4>{});
-    __syncthreads();
   }
 
   // ---- 5. divide and store
@@ -345,23 +479,41 @@ __global__ void __launch_bounds__(256) fused_kernel(const JobDesc job) {
       if (xx < Wd) dst[(size_t)yy * job.dst_pitch + xx] = (float)(P[j][i] / Q[j][i] + (Acc)c0);
     }
   }
+  (void)two_t;
+  (void)inv_two_t;
 }
 
 template <int PREC, int NT, int TH, bool INTEGER>
 hipError_t launch_t(const JobDesc& job, hipStream_t stream) {
-  dim3 grid((job.width + kTileCols - 1) / kTileCols, (job.height + TH - 1) / TH);
-  const size_t lds = sizeof(float2) * 2 * (size_t)job.T;
-  hipLaunchKernelGGL((fused_kernel<PREC, NT, TH, INTEGER>), grid, dim3(256), lds, stream, job);
+  using G = Geo<PREC, NT>;
+  static_assert(G::THREADS == kThreadsFor<PREC>, "launch bounds");
+  dim3 grid((job.width + G::COLS - 1) / G::COLS, (job.height + TH - 1) / TH);
+  const size_t dyn = dynamic_lds(job.T);
+  constexpr bool staged = INTEGER && Lds<PREC, NT, TH, true>::fits;
+  if (Lds<PREC, NT, TH, staged>::total + dyn > kLdsLimit) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((fused_kernel<PREC, NT, TH, INTEGER>), grid, dim3(G::THREADS), dyn, stream, job);
   return hipGetLastError();
+}
+
+// true when the staged (integer) variant with TH rows fits LDS for this T
+template <int PREC, int NT, int TH>
+bool staged_fits(int T) {
+  return Lds<PREC, NT, TH, true>::fits && Lds<PREC, NT, TH, true>::total + dynamic_lds(T) <= kLdsLimit;
 }
 
 }  // namespace fused_detail
 
 template <int PREC, int NT>
 hipError_t launch_fused_nt(const JobDesc& job, int th, hipStream_t stream) {
+  using namespace fused_detail;
   const bool integer = (job.flags & BF_FLAG_INTEGER_INPUT) != 0;
-  if (th <= 32) return integer ? fused_detail::launch_t<PREC, NT, 32, true>(job, stream) : fused_detail::launch_t<PREC, NT, 32, false>(job, stream);
-  return integer ? fused_detail::launch_t<PREC, NT, 64, true>(job, stream) : fused_detail::launch_t<PREC, NT, 64, false>(job, stream);
+  if (integer) {
+    if (th > 32 && staged_fits<PREC, NT, 64>(job.T)) return launch_t<PREC, NT, 64, true>(job, stream);
+    if (staged_fits<PREC, NT, 32>(job.T)) return launch_t<PREC, NT, 32, true>(job, stream);
+  }
+  // general path (also taken when the staged tile would not fit LDS); its
+  // per-pixel phase needs more registers, so it always uses 32-row tiles
+  return launch_t<PREC, NT, 32, false>(job, stream);
 }
 
 }  // namespace bf

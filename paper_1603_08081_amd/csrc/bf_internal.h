@@ -39,10 +39,9 @@ struct JobDesc {
   double d[BF_MAX_K + 1];       // coefficients d_0..d_K
 };
 
-// Geometry of the fused kernel: a workgroup of 4 waves owns a 64-column by
+// Geometry of the fused kernel: a workgroup owns a tile_cols(prec)-column by
 // `th`-row output tile; one wave owns a 16-column strip of it.
-constexpr int kWaves = 4;
-constexpr int kTileCols = 16 * kWaves;
+inline int tile_cols(bf_planes prec) { return prec == BF_PLANES_FP32 ? 64 : 128; }
 
 // number of 16-row tiles spanned by 16 output rows plus a W-row halo on each side
 inline int window_tiles(int W) {
