@@ -6,11 +6,12 @@ demodulate, accumulate, divide) over one batch of synthetic input that is
 already resident in HBM.  The default workload is 32 frames of 2160 x 3840
 (integer gray levels with smooth gradients), Gaussian spatial kernel
 sigma_s = 8 (W = 24), Gaussian range kernel sigma_r = 15, T = 255, K = 32,
-filtered in one batched call with 16-bit planes and float32 accumulation;
-the same batch is also timed with float32 planes for comparison.
+filtered in one batched call with float16 planes and float32 accumulation
+(float16 keeps the error below half a gray level here; bfloat16 planes are
+timed and checked alongside, and so are float32 planes).
 
 Prints ONE JSON line (rank 0).  Usage:
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision bf16|fp16|fp32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp16|bf16|fp32]
 """
 from __future__ import annotations
 
@@ -45,10 +46,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp32"])
+    ap.add_argument("--precision", default="fp16", choices=["bf16", "fp16", "fp32"],
+                    help="plane format of the headline number (fp16 meets the 0.5 gray-level bar "
+                         "on this workload; bf16 is timed and checked alongside)")
     ap.add_argument("--workload", default="frames32_2160x3840")
     ap.add_argument("--frames", type=int, default=None, help="use only the first N frames")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32-plane comparison")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the bfloat16-plane comparison")
     ap.add_argument("--no-check", action="store_true", help="skip the error check against the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -110,6 +114,14 @@ def main():
     log("%s planes: %.3f ms/step, %.1f Mpix/s" % (args.precision, ms, value))
 
     extra = {}
+    dstb = None
+    if not args.no_bf16 and args.precision != "bf16":
+        dstb = torch.empty_like(src)
+        msb = timed("bf16", dstb, args.steps, 1)
+        vb = px / (msb * 1e-3) / 1e6
+        log("bf16 planes: %.3f ms/step, %.1f Mpix/s" % (msb, vb))
+        extra["bf16_value"] = round(vb, 1)
+        extra["bf16_ms_per_step"] = round(msb, 3)
     if not args.no_fp32 and args.precision != "fp32":
         dst32 = torch.empty_like(src)
         ms32 = timed("fp32", dst32, max(2, args.steps // 4), 1)
@@ -140,7 +152,8 @@ def main():
         rows = np.unique(np.array([0, 1, W - 1, W, H // 2, H - W - 1, H - 2, H - 1] +
                                   list(np.random.default_rng(1).integers(0, H, 4))))
         pix = (rows[:, None] * Wd + np.arange(Wd)[None, :]).ravel()
-        errs16, errs32, errsd = [], [], []
+        outb = dstb.cpu().numpy() if dstb is not None else None
+        errs16, errs32, errsd, errsb = [], [], [], []
         for fi in sorted({0, n - 1}):
             ref = oracle.fourier(imgs[fi], wl["spatial"], wl["sigma_s"] or 1.0, W, d, wl["T"], pixels=pix)
             dire = oracle.direct(imgs[fi], wl["spatial"], wl["sigma_s"] or 1.0, W, wl["range_kind"],
@@ -149,10 +162,15 @@ def main():
             errsd.append(np.abs(out16[fi].ravel()[pix] - dire).max())
             if out32 is not None:
                 errs32.append(np.abs(out32[fi].ravel()[pix] - ref).max())
+            if outb is not None:
+                errsb.append(np.abs(outb[fi].ravel()[pix] - ref).max())
         extra["max_err_vs_fourier_fp64"] = float("%.4g" % max(errs16))
         extra["max_err_vs_direct_fp64"] = float("%.4g" % max(errsd))
         if errs32:
             extra["fp32_max_err_vs_fourier_fp64"] = float("%.4g" % max(errs32))
+        if errsb:
+            extra["bf16_max_err_vs_fourier_fp64"] = float("%.4g" % max(errsb))
+            extra["bf16_meets_0p5"] = bool(max(errsb) < 0.5)
         extra["err_sample"] = "all pixels of %d rows of frames %s" % (len(rows), sorted({0, n - 1}))
         extra["meets_0p5"] = bool(max(errs16) < 0.5)
 

@@ -1,5 +1,8 @@
 #pragma once
-// Fused shiftable bilateral filter for gfx950 (one image per launch).
+// Fused shiftable bilateral filter for gfx950 (one image per launch): the
+// shared-plane kernel, used for fp32 planes and for non-integer images
+// (16-bit planes on integer images use the barrier-free kernel of
+// bf_wave_impl.h).
 //
 // Computes eq. (9) of the paper through Algorithm 1 in its real (cos/sin)
 // form: with theta_k(j) = k w f(j), w = pi / T, and c0 = T / 2,
@@ -502,18 +505,5 @@ bool staged_fits(int T) {
 }
 
 }  // namespace fused_detail
-
-template <int PREC, int NT>
-hipError_t launch_fused_nt(const JobDesc& job, int th, hipStream_t stream) {
-  using namespace fused_detail;
-  const bool integer = (job.flags & BF_FLAG_INTEGER_INPUT) != 0;
-  if (integer) {
-    if (th > 32 && staged_fits<PREC, NT, 64>(job.T)) return launch_t<PREC, NT, 64, true>(job, stream);
-    if (staged_fits<PREC, NT, 32>(job.T)) return launch_t<PREC, NT, 32, true>(job, stream);
-  }
-  // general path (also taken when the staged tile would not fit LDS); its
-  // per-pixel phase needs more registers, so it always uses 32-row tiles
-  return launch_t<PREC, NT, 32, false>(job, stream);
-}
 
 }  // namespace bf

@@ -1,6 +1,6 @@
 // One explicit instantiation of the fused kernel launcher, selected at build
 // time by BF_INST_PREC (a bf_planes value) and BF_INST_NT (window tiles).
-#include "bf_fused_impl.h"
+#include "bf_wave_impl.h"
 
 #if !defined(BF_INST_PREC) || !defined(BF_INST_NT)
 #error "compile with -DBF_INST_PREC=<0|1|2> -DBF_INST_NT=<2..9>"

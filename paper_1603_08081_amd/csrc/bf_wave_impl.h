@@ -1,0 +1,325 @@
+#pragma once
+// Barrier-free tile kernel for 16-bit planes and integer gray levels.
+//
+// Same arithmetic as the shared-plane kernel in bf_fused_impl.h (eq. (9)
+// through Algorithm 1 in its real cos/sin form), organised so that every wave
+// works on its own: a wave owns a 16-column strip and builds the row-pass
+// MFMA operands of its strip directly in registers from per-harmonic tables
+// indexed by gray level, instead of reading planes that all waves wrote to
+// LDS.  The only workgroup-wide synchronisation left is one barrier per
+// harmonic (the tables are double-buffered by harmonic parity), so waves
+// drift freely and the matrix, vector and LDS work of different waves
+// overlaps.
+//
+// Per harmonic k and gray level f the tables hold, for float16 planes,
+// (cos, sin)(k w f) as an fp16 pair -- the (f - c0) cos and (f - c0) sin
+// planes are then formed with packed fp16 multiplies against a staged tile
+// of f - c0 (exact in fp16 for half-integers) -- and, for bfloat16 planes,
+// the four plane values rounded to bfloat16.  The demodulation table holds
+// d_k cos and d_k sin in fp32.
+#include "bf_fused_impl.h"
+
+namespace bf {
+namespace fused_detail {
+
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+
+constexpr int kWaveNW = 8;                       // waves per workgroup
+constexpr int kWaveThreads = 64 * kWaveNW;
+constexpr int kWaveCols = 16 * kWaveNW;          // output columns per tile
+
+template <int PREC, int NT>
+struct WaveGeo {
+  static constexpr bool FP16 = (PREC == BF_PLANES_FP16);
+  static constexpr int KS = (NT + 1) / 2;
+  static constexpr int LWU = 16 * (kWaveNW - 1) + 32 * KS;  // staged input columns
+  static constexpr int FW = LWU + 8;                         // padded row (u16 / fp16)
+  static constexpr int MODB = FP16 ? 4 : 8;                  // modulation-table entry bytes
+};
+
+// LDS use of one tile of TH rows: gray-level offsets (and f - c0 for fp16)
+template <int PREC, int NT, int TH>
+struct WaveLds {
+  using G = WaveGeo<PREC, NT>;
+  static constexpr int FROWS = 16 * (TH / 16 + NT - 1);
+  static constexpr size_t tile = (size_t)FROWS * G::FW * 2 * (G::FP16 ? 2 : 1);
+  static constexpr size_t total = tile + 4 * (2 * BF_MAX_W + 1) + 64;
+};
+
+// dynamic LDS: modulation tables [2][(T+1) x 8 B], demodulation tables
+// [2][(T+1) x 8 B], cos/sin(pi m / T) [2T x 8 B]
+inline size_t wave_dynamic_lds(int T) { return 32 * (size_t)(T + 1) + 16 * (size_t)T; }
+
+// One output tile (kWaveCols x TH at X0, Y0) of one image, all harmonics.
+// Every thread of the workgroup must call it (it contains barriers).
+template <int PREC, int NT, int TH>
+__device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, uint16_t* ftile_raw,
+                                          _Float16* vtile_raw, float* w1s, unsigned char* dyn) {
+  using G = WaveGeo<PREC, NT>;
+  using PT = Planes<PREC>;
+  using E = typename PT::E;
+  constexpr bool FP16 = G::FP16;
+  constexpr int KS = G::KS, LWU = G::LWU, FW = G::FW, MODB = G::MODB;
+  constexpr int NJ = TH / 16, NS = NJ + NT - 1, FROWS = 16 * NS;
+  auto ftile = reinterpret_cast<uint16_t(*)[FW]>(ftile_raw);
+  auto vtile = reinterpret_cast<_Float16(*)[FW]>(vtile_raw);
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63, g = lane >> 4, n16 = lane & 15;
+  const int x0 = X0 + 16 * wave;
+  const int W = job.W, T = job.T, K = job.K;
+  const int Wal = (W + 7) & ~7;
+  const int H = job.height, Wd = job.width;
+  const float* __restrict__ src = job.src;
+  const int sp = job.src_pitch;
+  const float c0 = job.c0;
+  const size_t span = 8 * (size_t)(T + 1);
+  float2* lut = reinterpret_cast<float2*>(dyn + 4 * span);
+
+  for (int m = tid; m < 2 * T; m += kWaveThreads) {
+    double s, c;
+    sincospi((double)m / (double)T, &s, &c);
+    lut[m] = make_float2((float)c, (float)s);
+  }
+  for (int t = tid; t <= 2 * W; t += kWaveThreads) w1s[t] = job.w1[t];
+  // stage the haloed tile once: folded borders, f clamped to [0, T]
+  for (int idx = tid; idx < FROWS * LWU; idx += kWaveThreads) {
+    const int r = idx / LWU, c = idx - r * LWU;
+    float v = src[(size_t)fold(Y0 - W + r, H) * sp + fold(X0 - Wal + c, Wd)];
+    v = fminf(fmaxf(v, 0.f), (float)T);  // NaN -> 0; the flag promises integers in [0, T]
+    const int f = (int)v;
+    ftile[r][c] = (uint16_t)(f * MODB);
+    if constexpr (FP16) vtile[r][c] = (_Float16)((float)f - c0);
+  }
+  __syncthreads();
+
+  auto wq = [&](int dd) -> float { return (dd >= -W && dd <= W) ? PT::round(w1s[dd + W]) : 0.f; };
+  typename PT::V8 brow[KS], bcol[KS];
+  for (int ks = 0; ks < KS; ++ks)
+    for (int e = 0; e < 8; ++e) {
+      brow[ks][e] = (E)wq(32 * ks + 8 * g + e - Wal - n16);
+      bcol[ks][e] = (E)wq(16 * (2 * ks + (e >> 2)) + 4 * g + (e & 3) - W - n16);
+    }
+  double wsum = 0.0;
+  for (int t = -W; t <= W; ++t) wsum += (double)wq(t);
+  const float q0 = (float)(job.d[0] * wsum * wsum);
+  // table byte offsets of this lane's output pixels, two per register
+  uint32_t fo[NJ][2];
+  for (int j = 0; j < NJ; ++j) {
+    const uint2 q = *reinterpret_cast<const uint2*>(&ftile[W + 16 * j + n16][Wal + 16 * wave + 4 * g]);
+    fo[j][0] = q.x;
+    fo[j][1] = q.y;
+  }
+  float P[NJ][4], Q[NJ][4];
+  for (int j = 0; j < NJ; ++j)
+    for (int i = 0; i < 4; ++i) P[j][i] = Q[j][i] = 0.f;
+
+  const PhaseTab pt{lut, 2.f * (float)T, 1.f / (2.f * (float)T), 1.f / (float)T, 2 * T};
+  auto tmod_k = [&](int kk) { return dyn + (size_t)(kk & 1) * span; };
+  auto tdem_k = [&](int kk) { return dyn + (size_t)(2 + (kk & 1)) * span; };
+  auto build = [&](int kk) {
+    unsigned char* tm = tmod_k(kk);
+    unsigned char* td = tdem_k(kk);
+    const float dkf = (float)job.d[kk];
+    for (int f = tid; f <= T; f += kWaveThreads) {
+      const float m = reduce_2t((float)kk * (float)f, pt);
+      const float2 cs = lut[min(max((int)m, 0), 2 * T - 1)];
+      const uint32_t w0 = PT::bits(cs.x) | (PT::bits(cs.y) << 16);
+      if constexpr (FP16) {
+        *reinterpret_cast<uint32_t*>(tm + MODB * f) = w0;
+      } else {
+        const float v = (float)f - c0;
+        const uint32_t w1 = PT::bits(v * cs.x) | (PT::bits(v * cs.y) << 16);
+        *reinterpret_cast<uint2*>(tm + MODB * f) = make_uint2(w0, w1);
+      }
+      *reinterpret_cast<float2*>(td + 8 * f) = make_float2(dkf * cs.x, dkf * cs.y);
+    }
+  };
+  // demodulation table offset of gray level f from its modulation offset
+  auto dem_off = [](uint32_t off) { return FP16 ? off * 2 : off; };
+
+  build(0);
+  if (K >= 1) build(1);
+  for (int k = 0; k <= K; ++k) {
+    __syncthreads();  // tables of harmonic k complete; every wave done with harmonic k - 1
+    if (k >= 1 && k + 1 <= K) build(k + 1);
+    const unsigned char* tm = tmod_k(k);
+    const unsigned char* td = tdem_k(k);
+    const float dk = (float)job.d[k];
+    auto run = [&](auto nplc) {
+      constexpr int NPL = decltype(nplc)::value;  // 1 for k = 0 (plane f - c0 only), else 4
+      typename PT::V4 ring[NT][NPL];
+      static_for<0, NS>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        // ---- row pass of step s: operands gathered straight into registers
+        f32x4 racc[NPL];
+        for (int pi = 0; pi < NPL; ++pi) racc[pi] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const int rr = 16 * s + n16, cc = 16 * wave + 32 * ks + 8 * g;
+          typename PT::V8 a;
+          uint32_t vq[4];
+          if constexpr (FP16) {
+            const uint4 v4 = *reinterpret_cast<const uint4*>(&vtile[rr][cc]);
+            vq[0] = v4.x; vq[1] = v4.y; vq[2] = v4.z; vq[3] = v4.w;
+          }
+          if constexpr (NPL == 4) {
+            const uint4 fq = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
+            const uint32_t fw[4] = {fq.x, fq.y, fq.z, fq.w};
+            uint32_t pc[4], ps[4], pfc[4], pfs[4];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {  // pixels 2h, 2h + 1
+              if constexpr (FP16) {
+                const uint32_t ta = *reinterpret_cast<const uint32_t*>(tm + (fw[h] & 0xffffu));
+                const uint32_t tb = *reinterpret_cast<const uint32_t*>(tm + (fw[h] >> 16));
+                pc[h] = (ta & 0xffffu) | (tb << 16);
+                ps[h] = (ta >> 16) | (tb & 0xffff0000u);
+                const h2v vv = __builtin_bit_cast(h2v, vq[h]);
+                pfc[h] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(h2v, pc[h]) * vv);
+                pfs[h] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(h2v, ps[h]) * vv);
+              } else {
+                const uint2 ta = *reinterpret_cast<const uint2*>(tm + (fw[h] & 0xffffu));
+                const uint2 tb = *reinterpret_cast<const uint2*>(tm + (fw[h] >> 16));
+                pc[h] = (ta.x & 0xffffu) | (tb.x << 16);
+                ps[h] = (ta.x >> 16) | (tb.x & 0xffff0000u);
+                pfc[h] = (ta.y & 0xffffu) | (tb.y << 16);
+                pfs[h] = (ta.y >> 16) | (tb.y & 0xffff0000u);
+              }
+            }
+            __builtin_memcpy(&a, pc, 16);
+            racc[0] = PT::mma(a, brow[ks], racc[0]);
+            __builtin_memcpy(&a, ps, 16);
+            racc[1] = PT::mma(a, brow[ks], racc[1]);
+            __builtin_memcpy(&a, pfc, 16);
+            racc[2] = PT::mma(a, brow[ks], racc[2]);
+            __builtin_memcpy(&a, pfs, 16);
+            racc[3] = PT::mma(a, brow[ks], racc[3]);
+          } else {
+            // harmonic 0: the single plane f - c0
+            if constexpr (FP16) {
+              __builtin_memcpy(&a, vq, 16);
+            } else {
+              const uint4 fq = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
+              const uint32_t fw[4] = {fq.x, fq.y, fq.z, fq.w};
+              uint32_t pv[4];
+#pragma unroll
+              for (int h = 0; h < 4; ++h) {
+                const float va = (float)((fw[h] & 0xffffu) / MODB) - c0;
+                const float vb = (float)((fw[h] >> 16) / MODB) - c0;
+                pv[h] = PT::bits(va) | (PT::bits(vb) << 16);
+              }
+              __builtin_memcpy(&a, pv, 16);
+            }
+            racc[0] = PT::mma(a, brow[ks], racc[0]);
+          }
+        }
+#pragma unroll
+        for (int pi = 0; pi < NPL; ++pi) {
+          typename PT::V4 v;
+          for (int i = 0; i < 4; ++i) v[i] = (E)racc[pi][i];
+          ring[s % NT][pi] = v;
+        }
+        // ---- column pass + demodulation of output tile j = s - NT + 1
+        if constexpr (s >= NT - 1) {
+          constexpr int j = s - NT + 1;
+          float fb[NPL][4];
+#pragma unroll
+          for (int pi = 0; pi < NPL; ++pi) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            static_for<0, KS>([&](auto kc) {
+              constexpr int ks = decltype(kc)::value;
+              typename PT::V4 lo = ring[(j + 2 * ks) % NT][pi];
+              typename PT::V4 hi;
+              if constexpr (2 * ks + 1 < NT) hi = ring[(j + 2 * ks + 1) % NT][pi];
+              else hi = typename PT::V4{(E)0.f, (E)0.f, (E)0.f, (E)0.f};
+              typename PT::V8 a = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+              acc = PT::mma(a, bcol[ks], acc);
+            });
+            for (int i = 0; i < 4; ++i) fb[pi][i] = acc[i];
+          }
+          if constexpr (NPL == 4) {
+            const uint32_t off[4] = {fo[j][0] & 0xffffu, fo[j][0] >> 16, fo[j][1] & 0xffffu, fo[j][1] >> 16};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float2 t = *reinterpret_cast<const float2*>(td + dem_off(off[i]));
+              P[j][i] = fmaf(t.x, fb[2][i], fmaf(t.y, fb[3][i], P[j][i]));
+              Q[j][i] = fmaf(t.x, fb[0][i], fmaf(t.y, fb[1][i], Q[j][i]));
+            }
+          } else {
+            for (int i = 0; i < 4; ++i) {
+              P[j][i] = fmaf(dk, fb[0][i], P[j][i]);
+              Q[j][i] += q0;
+            }
+          }
+        }
+      });
+    };
+    if (k == 0) run(std::integral_constant<int, 1>{});
+    else run(std::integral_constant<int, 4>{});
+  }
+
+  float* __restrict__ dst = job.dst;
+  for (int j = 0; j < NJ; ++j) {
+    const int yy = Y0 + 16 * j + n16;
+    if (yy >= H) continue;
+    for (int i = 0; i < 4; ++i) {
+      const int xx = x0 + 4 * g + i;
+      if (xx < Wd) dst[(size_t)yy * job.dst_pitch + xx] = P[j][i] / Q[j][i] + c0;
+    }
+  }
+  __syncthreads();  // the LDS of this tile may be reused by the caller
+}
+
+// variants whose staged tile cannot fit LDS even with the T = 255 tables are
+// compiled empty and never launched (the host checks wave_fits first)
+template <int PREC, int NT, int TH>
+constexpr bool kWaveBuildable = WaveLds<PREC, NT, TH>::total + 32 * 256 + 16 * 255 <= kLdsLimit;
+
+template <int PREC, int NT, int TH>
+__global__ void __launch_bounds__(kWaveThreads) wave_kernel(const JobDesc job) {
+  if constexpr (kWaveBuildable<PREC, NT, TH>) {
+    constexpr size_t TILE_ELEMS = WaveLds<PREC, NT, TH>::FROWS * WaveGeo<PREC, NT>::FW;
+    __shared__ __attribute__((aligned(16))) uint16_t ftile[TILE_ELEMS];
+    __shared__ __attribute__((aligned(16))) _Float16 vtile[WaveGeo<PREC, NT>::FP16 ? TILE_ELEMS : 8];
+    __shared__ float w1s[2 * BF_MAX_W + 1];
+    extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
+    wave_tile<PREC, NT, TH>(job, blockIdx.x * kWaveCols, blockIdx.y * TH, ftile, vtile, w1s, dyn);
+  }
+}
+
+template <int PREC, int NT, int TH>
+bool wave_fits(int T) {
+  return kWaveBuildable<PREC, NT, TH> && WaveLds<PREC, NT, TH>::total + wave_dynamic_lds(T) <= kLdsLimit;
+}
+
+template <int PREC, int NT, int TH>
+hipError_t launch_wave(const JobDesc& job, hipStream_t stream) {
+  dim3 grid((job.width + kWaveCols - 1) / kWaveCols, (job.height + TH - 1) / TH);
+  hipLaunchKernelGGL((wave_kernel<PREC, NT, TH>), grid, dim3(kWaveThreads), wave_dynamic_lds(job.T), stream, job);
+  return hipGetLastError();
+}
+
+}  // namespace fused_detail
+
+// Kernel choice for one image: 16-bit planes on integer gray levels take the
+// barrier-free kernel; fp32 planes take the shared-plane kernel with staged
+// tile and tables; non-integer images (or tiles that would not fit LDS) take
+// the general path of the shared-plane kernel.
+template <int PREC, int NT>
+hipError_t launch_fused_nt(const JobDesc& job, int th, hipStream_t stream) {
+  using namespace fused_detail;
+  const bool integer = (job.flags & BF_FLAG_INTEGER_INPUT) != 0;
+  if constexpr (PREC != BF_PLANES_FP32) {
+    if (integer) {
+      if (th > 32 && wave_fits<PREC, NT, 64>(job.T)) return launch_wave<PREC, NT, 64>(job, stream);
+      if (wave_fits<PREC, NT, 32>(job.T)) return launch_wave<PREC, NT, 32>(job, stream);
+    }
+  } else if (integer) {
+    if (th > 32 && staged_fits<PREC, NT, 64>(job.T)) return launch_t<PREC, NT, 64, true>(job, stream);
+    if (staged_fits<PREC, NT, 32>(job.T)) return launch_t<PREC, NT, 32, true>(job, stream);
+  }
+  // general path; its per-pixel phase needs more registers, so 32-row tiles
+  return launch_t<PREC, NT, 32, false>(job, stream);
+}
+
+}  // namespace bf
