@@ -138,32 +138,84 @@ typedef struct bf_job {
 } bf_job;
 
 /*
- * bf_workspace_bytes -- device workspace needed by bf_filter (n_jobs == 1)
- * or bf_filter_batched for these jobs and plane precision.  Returns 0 when
- * none is needed and (size_t)-1 when the jobs are invalid.
+ * bf_workspace_bytes -- device workspace that bf_filter_batched needs for
+ * these jobs and plane precision: the job table (one descriptor per image:
+ * pointers, sizes, W, K, T, the unit-sum spatial profile of eq. (2) and
+ * d_0..d_K) followed by the work items (one per output tile).  Runs the fits
+ * of jobs without d.  Returns (size_t)-1 when an argument is invalid
+ * (bf_last_error() says which).
  */
 size_t bf_workspace_bytes(const bf_job* jobs, int n_jobs, bf_planes prec);
 
 /*
- * bf_filter -- eq. (9) for one image via Algorithm 1, on the GPU.
- * Fits the range kernel first unless job->d is given.  workspace may be
- * NULL when bf_workspace_bytes() is 0.  Returns BF_OK, BF_FIT_NOT_CONVERGED
- * (filter ran with K = K_max), BF_E_INVALID, BF_E_UNSUPPORTED,
- * BF_E_WORKSPACE or BF_E_DEVICE.
+ * bf_filter -- eq. (9) for one image via Algorithm 1 (Sec. 2), on the GPU.
+ * Fits the range kernel first unless job->d is given (Algorithm 2), then runs
+ * one fused kernel over the image's output tiles: modulation by cos/sin of
+ * k w f (eq. (4)-(6), k = 0..K), separable smoothing of the planes with the
+ * spatial kernel (row then column pass), demodulation with d_k, accumulation
+ * of numerator and denominator of eq. (9) and the final division.
+ *   prec        plane format (BF_PLANES_*); accumulation is float32
+ *   workspace, ws_bytes   not used by the single-image path (its descriptor
+ *               travels as a kernel argument); may be NULL / 0
+ *   hip_stream  hipStream_t to enqueue on (NULL: the null stream)
+ * Asynchronous: returns after the enqueue; dst is written when the stream
+ * reaches the kernel.  Returns BF_OK, BF_FIT_NOT_CONVERGED (filter ran with
+ * K = K_max), BF_E_INVALID, BF_E_UNSUPPORTED or BF_E_DEVICE.  dst is not
+ * touched on a negative status.
  */
 int bf_filter(const bf_job* job, bf_planes prec, void* workspace, size_t ws_bytes, void* hip_stream);
 
 /*
  * bf_filter_batched -- eq. (9) for n_jobs independent images of any sizes,
- * each with its own spatial window, range kernel and K, in one launch of a
- * persistent kernel that pulls (image, tile) work items from a table.
- * The table is built on the host (fits included) and copied into the
- * workspace (asynchronously, from library-owned pinned memory).
- * Returns the first error found, else BF_FIT_NOT_CONVERGED if any job's fit
- * stopped at K_max, else BF_OK.
+ * each with its own spatial window, range kernel and K.  Every job is
+ * resolved on the host first (fits included); the images are cut into output
+ * tiles, the tiles grouped by kernel instantiation (window class, kernel
+ * family, tile height), and each group runs as ONE launch of a persistent
+ * kernel whose workgroups take tiles round-robin from a list ordered by
+ * decreasing cost 4K+1.  The job table and tile list are copied into
+ * `workspace` (device memory of at least bf_workspace_bytes() bytes,
+ * 16-byte aligned, owned by the caller) on `hip_stream`, asynchronously, from
+ * library-owned pinned memory; the caller must not reuse the workspace for
+ * anything else until the stream has passed the launches.
+ * Returns the first error found (nothing is enqueued then), else
+ * BF_FIT_NOT_CONVERGED if any job's fit stopped at K_max, else BF_OK.
  */
 int bf_filter_batched(const bf_job* jobs, int n_jobs, bf_planes prec,
                       void* workspace, size_t ws_bytes, void* hip_stream);
+
+/*
+ * Plans: bf_filter_batched split into its host part (done once) and its
+ * device part (repeated), for callers that filter the same buffers again and
+ * again (video frames written into the same src buffers, serving loops).
+ *
+ * bf_plan_create  resolves and fits every job and builds the tile list, as
+ *                 bf_filter_batched does; no GPU call.  *plan receives an
+ *                 opaque handle (NULL on error).  Returns BF_OK,
+ *                 BF_FIT_NOT_CONVERGED, BF_E_INVALID or BF_E_UNSUPPORTED.
+ *                 The plan keeps the jobs' src/dst pointers: they must stay
+ *                 valid while the plan is launched.
+ * bf_plan_workspace_bytes  workspace the plan needs ((size_t)-1 for NULL).
+ * bf_plan_upload  copies the job table into `workspace` on `hip_stream`
+ *                 (asynchronous, as in bf_filter_batched) and binds the plan
+ *                 to that workspace and to the stream's device.
+ * bf_plan_launch  enqueues the plan's launches on `hip_stream` (same device
+ *                 as the upload).  use_graph == 0: one launch per group,
+ *                 in order.  use_graph != 0: the first call captures the
+ *                 launches into a HIP graph (groups as independent kernel
+ *                 nodes, which may run concurrently) on streams of the
+ *                 library, later calls replay it with hipGraphLaunch; the
+ *                 graph holds kernel nodes only.  No allocation and no copy
+ *                 after the first graph launch.  Calls on one plan must not
+ *                 overlap in time from several host threads.
+ * bf_plan_destroy waits for the last graph replay of the plan to finish,
+ *                 then frees the plan (NULL is ignored).
+ */
+typedef struct bf_plan bf_plan;
+int bf_plan_create(const bf_job* jobs, int n_jobs, bf_planes prec, bf_plan** plan);
+size_t bf_plan_workspace_bytes(const bf_plan* plan);
+int bf_plan_upload(bf_plan* plan, void* workspace, size_t ws_bytes, void* hip_stream);
+int bf_plan_launch(bf_plan* plan, void* hip_stream, int use_graph);
+void bf_plan_destroy(bf_plan* plan);
 
 /* Thread-local text describing the last non-OK status of this thread. */
 const char* bf_last_error(void);

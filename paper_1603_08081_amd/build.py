@@ -22,7 +22,7 @@ ROOT = os.path.dirname(PKG)
 
 PRECS = (0, 1, 2)          # bf_planes: fp32, fp16, bf16
 NTS = tuple(range(2, 10))  # window tiles (W <= 64)
-HOST_SRCS = ("bf_api.cpp", "bf_fit.cpp", "bf_dispatch.cpp")
+HOST_SRCS = ("bf_api.cpp", "bf_batch.cpp", "bf_fit.cpp", "bf_dispatch.cpp")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -1,5 +1,6 @@
-// C ABI of libbf: argument checking, coefficient fit, spatial weights and
-// kernel dispatch.  See include/bf.h for the contract of each entry point.
+// C ABI of libbf: argument checking, coefficient fit, spatial weights and the
+// single-image entry point.  The batched entry points and plans live in
+// bf_batch.cpp.  See include/bf.h for the contract of each entry point.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -18,8 +19,6 @@ thread_local std::string g_error;
 }
 
 void set_error(const std::string& msg) { g_error = msg; }
-
-namespace {
 
 int fail(int code, const std::string& msg) {
   set_error(msg);
@@ -42,12 +41,6 @@ int check_fit_args(bf_range_kind kind, double sigma_r, const double* table, int 
   }
   return BF_OK;
 }
-
-// Everything bf_filter needs, resolved from a bf_job.
-struct Resolved {
-  JobDesc desc;
-  int status = BF_OK;  // BF_OK or BF_FIT_NOT_CONVERGED
-};
 
 int resolve_job(const bf_job* j, Resolved* out) {
   if (!j) return fail(BF_E_INVALID, "job is NULL");
@@ -135,7 +128,6 @@ int pick_tile_rows(const JobDesc& jd, bf_planes prec) {
   return blocks64 >= 512 ? 64 : 32;
 }
 
-}  // namespace
 }  // namespace bf
 
 using namespace bf;
@@ -162,16 +154,6 @@ extern "C" int bf_fit_coeffs(bf_range_kind kind, double sigma_r, const double* p
   return BF_OK;
 }
 
-extern "C" size_t bf_workspace_bytes(const bf_job* jobs, int n_jobs, bf_planes prec) {
-  if (!jobs || n_jobs < 1) return (size_t)-1;
-  if (prec != BF_PLANES_FP32 && prec != BF_PLANES_FP16 && prec != BF_PLANES_BF16) return (size_t)-1;
-  for (int i = 0; i < n_jobs; ++i) {
-    Resolved r;
-    if (resolve_job(&jobs[i], &r) < 0) return (size_t)-1;
-  }
-  return 0;
-}
-
 extern "C" int bf_filter(const bf_job* job, bf_planes prec, void* workspace, size_t ws_bytes,
                          void* hip_stream) {
   (void)workspace;
@@ -185,21 +167,4 @@ extern "C" int bf_filter(const bf_job* job, bf_planes prec, void* workspace, siz
   if (e != hipSuccess) return fail(BF_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
   if (r.status != BF_OK) set_error("fit stopped at K_max with ||b - A d|| > eps");
   return r.status;
-}
-
-extern "C" int bf_filter_batched(const bf_job* jobs, int n_jobs, bf_planes prec, void* workspace,
-                                 size_t ws_bytes, void* hip_stream) {
-  if (!jobs || n_jobs < 1) return fail(BF_E_INVALID, "jobs must be non-NULL and n_jobs >= 1");
-  int worst = BF_OK;
-  for (int i = 0; i < n_jobs; ++i) {
-    Resolved r;
-    int rc = resolve_job(&jobs[i], &r);
-    if (rc < 0) return rc;
-  }
-  for (int i = 0; i < n_jobs; ++i) {
-    int rc = bf_filter(&jobs[i], prec, workspace, ws_bytes, hip_stream);
-    if (rc < 0) return rc;
-    if (rc > worst) worst = rc;
-  }
-  return worst;
 }

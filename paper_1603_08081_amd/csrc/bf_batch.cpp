@@ -1,0 +1,397 @@
+// Batched filtering: plans, the job table in the caller's workspace, and the
+// persistent per-class launches (one HIP graph per plan when asked for).
+//
+// A plan resolves every job on the host (arguments, W, the Algorithm 2 fit,
+// the unit-sum spatial profile), picks each job's kernel family and tile
+// geometry, and cuts every image into output tiles ("work items").  Items are
+// grouped into classes that share one kernel instantiation (window class NT,
+// family, tile height); inside a class the jobs are ordered by decreasing
+// number of planes 4K+1, so a persistent grid that takes items round-robin
+// gives every workgroup a similar load.  The descriptor table and the items
+// are copied once into the caller's workspace:
+//
+//   [ JobDesc x n_jobs | pad to 256 B | int4 items (job, x0, y0, 0) ]
+//
+// The copy is staged through library-owned pinned host memory.  A staging
+// buffer is reused only after the event recorded behind its copy has
+// completed; one whose copy was recorded into a stream capture is never
+// reused (the captured copy node keeps reading it).  The pool is never freed
+// before process exit, which avoids calling into the HIP runtime from static
+// destructors.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "bf_internal.h"
+
+namespace bf {
+namespace {
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct ClassLaunch {
+  int nt;          // window class: 16-row tiles spanned by 16 rows + 2W halo
+  TileChoice tc;   // kernel family and tile geometry
+  int t_max;       // largest T among the class's jobs (sizes the dynamic LDS)
+  size_t item_off; // first item of the class
+  int n_items;
+  double cost;     // sum over items of (4K+1) x tile area, for ordering
+};
+
+struct PlanData {
+  bf_planes prec = BF_PLANES_FP32;
+  std::vector<JobDesc> descs;
+  std::vector<int4> items;
+  std::vector<ClassLaunch> classes;
+  int status = BF_OK;      // BF_OK or BF_FIT_NOT_CONVERGED
+  size_t items_off = 0;    // byte offset of the items in the workspace
+  size_t ws_bytes = 0;
+  int grid = 0;            // 0: occupancy-sized persistent grid; -1: one item per workgroup
+};
+
+// Workgroups per class launch.  BF_BATCH_GRID=items gives one workgroup per
+// item (the hardware dispatcher balances the load); a positive number fixes
+// the grid; the default sizes a persistent grid from the occupancy.
+int grid_mode_from_env() {
+  const char* s = std::getenv("BF_BATCH_GRID");
+  if (!s || !*s) return 0;
+  if (std::strcmp(s, "items") == 0) return -1;
+  const int v = std::atoi(s);
+  return v > 0 ? v : 0;
+}
+
+int valid_prec(bf_planes prec) {
+  return prec == BF_PLANES_FP32 || prec == BF_PLANES_FP16 || prec == BF_PLANES_BF16;
+}
+
+int build_plan(const bf_job* jobs, int n_jobs, bf_planes prec, PlanData& p) {
+  if (!jobs || n_jobs < 1) return fail(BF_E_INVALID, "jobs must be non-NULL and n_jobs >= 1");
+  if (!valid_prec(prec)) return fail(BF_E_INVALID, "unknown plane precision");
+  p = PlanData{};
+  p.prec = prec;
+  p.grid = grid_mode_from_env();
+  p.descs.resize(n_jobs);
+  std::vector<TileChoice> choice(n_jobs);
+  std::map<long, std::vector<int>> by_class;  // key (nt, family, th) -> jobs
+  for (int i = 0; i < n_jobs; ++i) {
+    Resolved r;
+    const int rc = resolve_job(&jobs[i], &r);
+    if (rc < 0) {
+      set_error("job " + std::to_string(i) + ": " + bf_last_error());
+      return rc;
+    }
+    if (r.status > p.status) p.status = r.status;
+    p.descs[i] = r.desc;
+    const int nt = window_tiles(r.desc.W);
+    // fp32 planes with wide windows need too many registers for 64-row tiles
+    const int th_pref = (prec == BF_PLANES_FP32 && nt >= 5) ? 32 : 64;
+    choice[i] = choose_tile(r.desc, prec, th_pref);
+    const long key = (long)nt * 10000 + choice[i].family * 1000 + choice[i].th;
+    by_class[key].push_back(i);
+  }
+  for (auto& kv : by_class) {
+    std::vector<int>& js = kv.second;
+    std::stable_sort(js.begin(), js.end(), [&](int a, int b) { return p.descs[a].K > p.descs[b].K; });
+    ClassLaunch c{};
+    c.nt = static_cast<int>(kv.first / 10000);
+    c.tc = choice[js[0]];
+    c.item_off = p.items.size();
+    for (int j : js) {
+      const JobDesc& d = p.descs[j];
+      c.t_max = std::max(c.t_max, d.T);
+      for (int y0 = 0; y0 < d.height; y0 += c.tc.th)
+        for (int x0 = 0; x0 < d.width; x0 += c.tc.cols) {
+          p.items.push_back(make_int4(j, x0, y0, 0));
+          c.cost += (4.0 * d.K + 1.0) * c.tc.th * c.tc.cols;
+        }
+    }
+    c.n_items = static_cast<int>(p.items.size() - c.item_off);
+    if (p.items.size() > (size_t)INT32_MAX) return fail(BF_E_UNSUPPORTED, "too many tiles in one batch");
+    p.classes.push_back(c);
+  }
+  // most expensive class first: when launched one after another its tail is
+  // followed by cheaper work
+  std::stable_sort(p.classes.begin(), p.classes.end(),
+                   [](const ClassLaunch& a, const ClassLaunch& b) { return a.cost > b.cost; });
+  p.items_off = align_up(sizeof(JobDesc) * (size_t)n_jobs, 256);
+  p.ws_bytes = p.items_off + sizeof(int4) * p.items.size();
+  return BF_OK;
+}
+
+// ---- pinned staging of the job table --------------------------------------
+struct StagingSlot {
+  void* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  int device = -1;
+  bool recorded = false;  // ev recorded behind the last copy
+  bool retired = false;   // read by a captured copy node: never reused
+};
+
+std::mutex g_staging_mutex;
+std::vector<StagingSlot*>* g_staging = new std::vector<StagingSlot*>();  // never freed (see top)
+
+int stream_device(hipStream_t s, int* dev) {
+  hipError_t e = s ? hipStreamGetDevice(s, dev) : hipGetDevice(dev);
+  if (e != hipSuccess) return fail(BF_E_DEVICE, std::string("cannot query the stream's device: ") + hipGetErrorString(e));
+  return BF_OK;
+}
+
+struct DeviceGuard {
+  int saved = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&saved) != hipSuccess) saved = -1;
+    if (saved != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (saved >= 0 && hipGetDevice(&cur) == hipSuccess && cur != saved) (void)hipSetDevice(saved);
+  }
+};
+
+// Copies the plan's table into `workspace` on `stream` (asynchronously);
+// *device_out receives the stream's device.  Arguments are checked before any
+// HIP call.
+int upload_table(const PlanData& p, void* workspace, size_t ws_bytes, hipStream_t stream, int* device_out) {
+  if (!workspace) return fail(BF_E_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < p.ws_bytes)
+    return fail(BF_E_WORKSPACE, "workspace smaller than bf_workspace_bytes() = " + std::to_string(p.ws_bytes));
+  if (reinterpret_cast<uintptr_t>(workspace) % 16 != 0)
+    return fail(BF_E_WORKSPACE, "workspace must be 16-byte aligned");
+  int dev = 0;
+  int rc = stream_device(stream, &dev);
+  if (rc != BF_OK) return rc;
+  if (device_out) *device_out = dev;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (stream && hipStreamIsCapturing(stream, &cs) != hipSuccess) cs = hipStreamCaptureStatusNone;
+
+  std::lock_guard<std::mutex> lock(g_staging_mutex);
+  StagingSlot* slot = nullptr;
+  for (StagingSlot* s : *g_staging) {
+    if (s->retired || s->device != dev || s->cap < p.ws_bytes) continue;
+    if (s->recorded) {
+      const hipError_t q = hipEventQuery(s->ev);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) continue;  // leave a slot with a failed event alone
+    }
+    slot = s;
+    break;
+  }
+  if (!slot) {
+    DeviceGuard g(dev);
+    slot = new StagingSlot();
+    slot->device = dev;
+    slot->cap = align_up(std::max<size_t>(p.ws_bytes, 64 << 10), 4096);
+    hipError_t e = hipHostMalloc(&slot->host, slot->cap, hipHostMallocPortable);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&slot->ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      if (slot->host) (void)hipHostFree(slot->host);
+      delete slot;
+      return fail(BF_E_DEVICE, std::string("pinned staging allocation failed: ") + hipGetErrorString(e));
+    }
+    g_staging->push_back(slot);
+  }
+  unsigned char* h = static_cast<unsigned char*>(slot->host);
+  std::memcpy(h, p.descs.data(), sizeof(JobDesc) * p.descs.size());
+  std::memset(h + sizeof(JobDesc) * p.descs.size(), 0, p.items_off - sizeof(JobDesc) * p.descs.size());
+  std::memcpy(h + p.items_off, p.items.data(), sizeof(int4) * p.items.size());
+  hipError_t e = hipMemcpyAsync(workspace, h, p.ws_bytes, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return fail(BF_E_DEVICE, std::string("job table copy failed: ") + hipGetErrorString(e));
+  if (cs != hipStreamCaptureStatusNone) {
+    slot->retired = true;
+    slot->recorded = false;
+  } else {
+    e = hipEventRecord(slot->ev, stream);
+    if (e != hipSuccess) {
+      slot->retired = true;  // cannot tell when the copy ends
+      return fail(BF_E_DEVICE, std::string("event record failed: ") + hipGetErrorString(e));
+    }
+    slot->recorded = true;
+  }
+  return BF_OK;
+}
+
+int launch_class(const PlanData& p, const ClassLaunch& c, const void* workspace, hipStream_t stream) {
+  const unsigned char* ws = static_cast<const unsigned char*>(workspace);
+  const JobDesc* jobs = reinterpret_cast<const JobDesc*>(ws);
+  const int4* items = reinterpret_cast<const int4*>(ws + p.items_off) + c.item_off;
+  const int grid = p.grid < 0 ? c.n_items : p.grid;
+  hipError_t e = launch_batched(jobs, items, c.n_items, c.t_max, p.prec, c.nt, c.tc, grid, stream);
+  if (e != hipSuccess) return fail(BF_E_DEVICE, std::string("batched kernel launch failed: ") + hipGetErrorString(e));
+  return BF_OK;
+}
+
+int launch_all(const PlanData& p, const void* workspace, hipStream_t stream) {
+  for (const ClassLaunch& c : p.classes) {
+    int rc = launch_class(p, c, workspace, stream);
+    if (rc != BF_OK) return rc;
+  }
+  return BF_OK;
+}
+
+}  // namespace
+}  // namespace bf
+
+using namespace bf;
+
+struct bf_plan {
+  PlanData p;
+  void* ws = nullptr;   // device workspace of the last upload
+  int device = -1;
+  // graph form: classes as independent kernel nodes of one graph
+  hipGraphExec_t exec = nullptr;
+  hipStream_t capture = nullptr;
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
+  hipEvent_t done = nullptr;
+  bool launched = false;
+
+  void drop_graph() {
+    if (exec) {
+      if (launched && done) (void)hipEventSynchronize(done);
+      (void)hipGraphExecDestroy(exec);
+      exec = nullptr;
+    }
+    launched = false;
+  }
+  ~bf_plan() {
+    drop_graph();
+    for (hipStream_t s : side) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : join) (void)hipEventDestroy(e);
+    if (capture) (void)hipStreamDestroy(capture);
+    if (fork) (void)hipEventDestroy(fork);
+    if (done) (void)hipEventDestroy(done);
+  }
+
+  // Captures the class launches on library streams: class 0 on the capture
+  // stream, every other class on a side stream forked from it and joined back,
+  // so the graph holds them as independent nodes that may run concurrently.
+  int build_graph() {
+    DeviceGuard g(device);
+    hipError_t e = hipSuccess;
+    if (!capture) e = hipStreamCreateWithFlags(&capture, hipStreamNonBlocking);
+    if (e == hipSuccess && !fork) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e == hipSuccess && !done) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    while (e == hipSuccess && side.size() + 1 < p.classes.size()) {
+      hipStream_t s = nullptr;
+      hipEvent_t ev = nullptr;
+      e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+      if (e != hipSuccess) break;
+      side.push_back(s);
+      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e != hipSuccess) break;
+      join.push_back(ev);
+    }
+    if (e != hipSuccess) return fail(BF_E_DEVICE, std::string("graph resources: ") + hipGetErrorString(e));
+    e = hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(BF_E_DEVICE, std::string("stream capture: ") + hipGetErrorString(e));
+    int rc = BF_OK;
+    if (p.classes.size() > 1) {
+      e = hipEventRecord(fork, capture);
+      if (e != hipSuccess) rc = fail(BF_E_DEVICE, std::string("capture fork: ") + hipGetErrorString(e));
+    }
+    for (size_t c = 0; rc == BF_OK && c < p.classes.size(); ++c) {
+      hipStream_t s = c == 0 ? capture : side[c - 1];
+      if (c > 0 && (e = hipStreamWaitEvent(s, fork, 0)) != hipSuccess) {
+        rc = fail(BF_E_DEVICE, std::string("capture fork: ") + hipGetErrorString(e));
+        break;
+      }
+      rc = launch_class(p, p.classes[c], ws, s);
+      if (rc == BF_OK && c > 0) {
+        e = hipEventRecord(join[c - 1], s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(capture, join[c - 1], 0);
+        if (e != hipSuccess) rc = fail(BF_E_DEVICE, std::string("capture join: ") + hipGetErrorString(e));
+      }
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(capture, &graph);
+    if (rc == BF_OK && e != hipSuccess) rc = fail(BF_E_DEVICE, std::string("end capture: ") + hipGetErrorString(e));
+    if (rc == BF_OK) {
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        exec = nullptr;
+        rc = fail(BF_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+      }
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+};
+
+extern "C" size_t bf_workspace_bytes(const bf_job* jobs, int n_jobs, bf_planes prec) {
+  PlanData p;
+  if (build_plan(jobs, n_jobs, prec, p) < 0) return (size_t)-1;
+  return p.ws_bytes;
+}
+
+extern "C" int bf_filter_batched(const bf_job* jobs, int n_jobs, bf_planes prec, void* workspace,
+                                 size_t ws_bytes, void* hip_stream) {
+  PlanData p;
+  int rc = build_plan(jobs, n_jobs, prec, p);
+  if (rc < 0) return rc;
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  rc = upload_table(p, workspace, ws_bytes, stream, nullptr);
+  if (rc < 0) return rc;
+  rc = launch_all(p, workspace, stream);
+  if (rc < 0) return rc;
+  if (p.status != BF_OK) set_error("a fit stopped at K_max with ||b - A d|| > eps");
+  return p.status;
+}
+
+extern "C" int bf_plan_create(const bf_job* jobs, int n_jobs, bf_planes prec, bf_plan** plan) {
+  if (!plan) return fail(BF_E_INVALID, "plan must be non-NULL");
+  *plan = nullptr;
+  bf_plan* pl = new bf_plan();
+  int rc = build_plan(jobs, n_jobs, prec, pl->p);
+  if (rc < 0) {
+    delete pl;
+    return rc;
+  }
+  *plan = pl;
+  if (pl->p.status != BF_OK) set_error("a fit stopped at K_max with ||b - A d|| > eps");
+  return pl->p.status;
+}
+
+extern "C" size_t bf_plan_workspace_bytes(const bf_plan* plan) { return plan ? plan->p.ws_bytes : (size_t)-1; }
+
+extern "C" int bf_plan_upload(bf_plan* plan, void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (!plan) return fail(BF_E_INVALID, "plan is NULL");
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  int dev = -1;
+  const int rc = upload_table(plan->p, workspace, ws_bytes, stream, &dev);
+  if (rc != BF_OK) return rc;
+  if (plan->ws != workspace || plan->device != dev) plan->drop_graph();
+  plan->ws = workspace;
+  plan->device = dev;
+  return BF_OK;
+}
+
+extern "C" int bf_plan_launch(bf_plan* plan, void* hip_stream, int use_graph) {
+  if (!plan) return fail(BF_E_INVALID, "plan is NULL");
+  if (!plan->ws) return fail(BF_E_INVALID, "bf_plan_upload must precede bf_plan_launch");
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  int dev = 0;
+  int rc = stream_device(stream, &dev);
+  if (rc != BF_OK) return rc;
+  if (dev != plan->device) return fail(BF_E_INVALID, "stream belongs to another device than the uploaded table");
+  if (!use_graph) return launch_all(plan->p, plan->ws, stream);
+  if (!plan->exec) {
+    rc = plan->build_graph();
+    if (rc != BF_OK) return rc;
+  }
+  hipError_t e = hipGraphLaunch(plan->exec, stream);
+  if (e == hipSuccess) e = hipEventRecord(plan->done, stream);
+  if (e != hipSuccess) return fail(BF_E_DEVICE, std::string("graph launch failed: ") + hipGetErrorString(e));
+  plan->launched = true;
+  return BF_OK;
+}
+
+extern "C" void bf_plan_destroy(bf_plan* plan) { delete plan; }

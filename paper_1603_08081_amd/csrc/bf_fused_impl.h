@@ -172,8 +172,14 @@ __device__ __forceinline__ void phase_general(float kf, float f, const PhaseTab&
   s = v.y * cr + v.x * sr;
 }
 
+// One output tile (COLS x TH at X0, Y0) of one image, all harmonics.  smem
+// holds the plane buffers, the staged tile and the spatial profile (layout of
+// Lds<>); tab has room for (T+1) 16-byte entries; lut holds cos/sin(pi m / T),
+// rebuilt here when build_lut is set.  Every thread of the workgroup must call
+// it (it contains barriers).
 template <int PREC, int NT, int TH, bool INTEGER_REQ>
-__global__ void __launch_bounds__(kThreadsFor<PREC>) fused_kernel(const JobDesc job) {
+__device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, unsigned char* smem,
+                                           unsigned char* tab, float2* lut, bool build_lut) {
   constexpr bool INTEGER = INTEGER_REQ && Lds<PREC, NT, TH, true>::fits;
   using G = Geo<PREC, NT>;
   using PT = Planes<PREC>;
@@ -184,16 +190,14 @@ __global__ void __launch_bounds__(kThreadsFor<PREC>) fused_kernel(const JobDesc 
   constexpr int NS = NJ + NT - 1;        // 16-row steps per harmonic
   constexpr int FROWS = 16 * NS;         // staged image rows
 
-  __shared__ __attribute__((aligned(16))) E planes[2][4][16][LW];
+  using L = Lds<PREC, NT, TH, INTEGER>;
+  auto planes = reinterpret_cast<E(*)[4][16][LW]>(smem);
   // image tile, stored as f * kTabBytes (byte offset of gray level f in the table)
-  __shared__ __attribute__((aligned(16))) uint16_t ftile[INTEGER ? FROWS : 1][INTEGER ? FW : 8];
-  __shared__ float w1s[2 * BF_MAX_W + 1];
-  // dynamic: per-harmonic table [(T+1) x 16 B], then cos/sin(pi m / T) [2T x 8 B]
-  extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
+  auto ftile = reinterpret_cast<uint16_t(*)[INTEGER ? FW : 8]>(smem + L::planes);
+  float* w1s = reinterpret_cast<float*>(smem + L::planes + L::tile);
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, g = lane >> 4, n16 = lane & 15;
-  const int X0 = blockIdx.x * G::COLS, Y0 = blockIdx.y * TH;
   const int x0 = X0 + 16 * wave;
   const int W = job.W, T = job.T, K = job.K;
   const int Wal = (W + 7) & ~7;          // column origin of the staged tile: X0 - Wal
@@ -201,10 +205,7 @@ __global__ void __launch_bounds__(kThreadsFor<PREC>) fused_kernel(const JobDesc 
   const float* __restrict__ src = job.src;
   const int sp = job.src_pitch;
   const float c0 = job.c0;
-  unsigned char* tab = dyn;
-  float2* lut = reinterpret_cast<float2*>(dyn + (size_t)kTabBytes * (T + 1));
-
-  for (int m = tid; m < 2 * T; m += NTHR) {
+  for (int m = tid; m < (build_lut ? 2 * T : 0); m += NTHR) {
     double s, c;
     sincospi((double)m / (double)T, &s, &c);
     lut[m] = make_float2((float)c, (float)s);
@@ -484,6 +485,38 @@ __global__ void __launch_bounds__(kThreadsFor<PREC>) fused_kernel(const JobDesc 
   }
   (void)two_t;
   (void)inv_two_t;
+  __syncthreads();  // the LDS of this tile may be reused by the caller
+}
+
+template <int PREC, int NT, int TH, bool INTEGER>
+__global__ void __launch_bounds__(kThreadsFor<PREC>) fused_kernel(const JobDesc job) {
+  constexpr bool staged = INTEGER && Lds<PREC, NT, TH, true>::fits;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[Lds<PREC, NT, TH, staged>::total];
+  // dynamic: per-harmonic table [(T+1) x 16 B], then cos/sin(pi m / T) [2T x 8 B]
+  extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
+  fused_tile<PREC, NT, TH, INTEGER>(job, blockIdx.x * Geo<PREC, NT>::COLS, blockIdx.y * TH, smem, dyn,
+                                    reinterpret_cast<float2*>(dyn + (size_t)kTabBytes * (job.T + 1)), true);
+}
+
+// Persistent form: workgroup b processes items b, b + gridDim.x, ... of a
+// cost-ordered list; item = (job index, tile x0, tile y0, -).  Dynamic LDS:
+// cos/sin table for T_max first, then the per-harmonic table.
+template <int PREC, int NT, int TH, bool INTEGER>
+__global__ void __launch_bounds__(kThreadsFor<PREC>) fused_batched_kernel(const JobDesc* __restrict__ jobs,
+                                                                        const int4* __restrict__ items,
+                                                                        int n_items, int t_max) {
+  constexpr bool staged = INTEGER && Lds<PREC, NT, TH, true>::fits;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[Lds<PREC, NT, TH, staged>::total];
+  extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
+  float2* lut = reinterpret_cast<float2*>(dyn);
+  unsigned char* tab = dyn + 16 * (size_t)t_max;
+  int lut_t = -1;
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int4 w = items[it];
+    const JobDesc& job = jobs[w.x];
+    fused_tile<PREC, NT, TH, INTEGER>(job, w.y, w.z, smem, tab, lut, job.T != lut_t);
+    lut_t = job.T;
+  }
 }
 
 template <int PREC, int NT, int TH, bool INTEGER>

@@ -49,10 +49,36 @@ inline int window_tiles(int W) {
   return nt < 2 ? 2 : nt;
 }
 
-// launchers (bf_kernels*.hip); return the hipError_t of the launch
+// launchers (bf_fused_inst.hip instantiations); return the hipError_t of the launch
 hipError_t launch_fused(const JobDesc& job, bf_planes prec, int th, hipStream_t stream);
+
+// Tile geometry and kernel family chosen for one job: family 1 = barrier-free
+// wave kernel, 2 = shared-plane kernel with staged tile, 0 = general path.
+struct TileChoice {
+  int cols, th, family;
+};
+TileChoice choose_tile(const JobDesc& job, bf_planes prec, int th_pref);
+// one persistent launch over n_items work items (int4: job, x0, y0, -) that
+// share window class, plane format and TileChoice; grid = workgroups
+hipError_t launch_batched(const JobDesc* jobs_dev, const int4* items_dev, int n_items, int t_max,
+                          bf_planes prec, int window_tiles, TileChoice tc, int grid, hipStream_t stream);
 
 // thread-local error text
 void set_error(const std::string& msg);
+// set_error(msg) and return code
+int fail(int code, const std::string& msg);
+
+// argument checks of Algorithm 2's inputs; BF_OK or a negative status
+int check_fit_args(bf_range_kind kind, double sigma_r, const double* table, int T, double eps, int K_max);
+
+// Everything the kernels need, resolved from a bf_job (validation, W, fit).
+struct Resolved {
+  JobDesc desc;
+  int status = BF_OK;  // BF_OK or BF_FIT_NOT_CONVERGED
+};
+int resolve_job(const bf_job* j, Resolved* out);
+
+// output-tile height for bf_filter (32 or 64 rows)
+int pick_tile_rows(const JobDesc& jd, bf_planes prec);
 
 }  // namespace bf

@@ -46,15 +46,18 @@ struct WaveLds {
   static constexpr size_t total = tile + 4 * (2 * BF_MAX_W + 1) + 64;
 };
 
-// dynamic LDS: modulation tables [2][(T+1) x 8 B], demodulation tables
-// [2][(T+1) x 8 B], cos/sin(pi m / T) [2T x 8 B]
+// dynamic LDS: cos/sin(pi m / T) [2T x 8 B], then the modulation tables
+// [2][(T+1) x 8 B] and the demodulation tables [2][(T+1) x 8 B]
 inline size_t wave_dynamic_lds(int T) { return 32 * (size_t)(T + 1) + 16 * (size_t)T; }
 
 // One output tile (kWaveCols x TH at X0, Y0) of one image, all harmonics.
-// Every thread of the workgroup must call it (it contains barriers).
+// tab has room for 4 (T+1) 8-byte entries; lut holds cos/sin(pi m / T),
+// rebuilt here when build_lut is set.  Every thread of the workgroup must
+// call it (it contains barriers).
 template <int PREC, int NT, int TH>
 __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, uint16_t* ftile_raw,
-                                          _Float16* vtile_raw, float* w1s, unsigned char* dyn) {
+                                          _Float16* vtile_raw, float* w1s, unsigned char* tab,
+                                          float2* lut, bool build_lut) {
   using G = WaveGeo<PREC, NT>;
   using PT = Planes<PREC>;
   using E = typename PT::E;
@@ -74,9 +77,8 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
   const int sp = job.src_pitch;
   const float c0 = job.c0;
   const size_t span = 8 * (size_t)(T + 1);
-  float2* lut = reinterpret_cast<float2*>(dyn + 4 * span);
 
-  for (int m = tid; m < 2 * T; m += kWaveThreads) {
+  for (int m = tid; m < (build_lut ? 2 * T : 0); m += kWaveThreads) {
     double s, c;
     sincospi((double)m / (double)T, &s, &c);
     lut[m] = make_float2((float)c, (float)s);
@@ -115,8 +117,8 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
     for (int i = 0; i < 4; ++i) P[j][i] = Q[j][i] = 0.f;
 
   const PhaseTab pt{lut, 2.f * (float)T, 1.f / (2.f * (float)T), 1.f / (float)T, 2 * T};
-  auto tmod_k = [&](int kk) { return dyn + (size_t)(kk & 1) * span; };
-  auto tdem_k = [&](int kk) { return dyn + (size_t)(2 + (kk & 1)) * span; };
+  auto tmod_k = [&](int kk) { return tab + (size_t)(kk & 1) * span; };
+  auto tdem_k = [&](int kk) { return tab + (size_t)(2 + (kk & 1)) * span; };
   auto build = [&](int kk) {
     unsigned char* tm = tmod_k(kk);
     unsigned char* td = tdem_k(kk);
@@ -273,7 +275,8 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
 // variants whose staged tile cannot fit LDS even with the T = 255 tables are
 // compiled empty and never launched (the host checks wave_fits first)
 template <int PREC, int NT, int TH>
-constexpr bool kWaveBuildable = WaveLds<PREC, NT, TH>::total + 32 * 256 + 16 * 255 <= kLdsLimit;
+constexpr bool kWaveBuildable =
+    PREC != BF_PLANES_FP32 && WaveLds<PREC, NT, TH>::total + 32 * 256 + 16 * 255 <= kLdsLimit;
 
 template <int PREC, int NT, int TH>
 __global__ void __launch_bounds__(kWaveThreads) wave_kernel(const JobDesc job) {
@@ -283,7 +286,33 @@ __global__ void __launch_bounds__(kWaveThreads) wave_kernel(const JobDesc job) {
     __shared__ __attribute__((aligned(16))) _Float16 vtile[WaveGeo<PREC, NT>::FP16 ? TILE_ELEMS : 8];
     __shared__ float w1s[2 * BF_MAX_W + 1];
     extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
-    wave_tile<PREC, NT, TH>(job, blockIdx.x * kWaveCols, blockIdx.y * TH, ftile, vtile, w1s, dyn);
+    wave_tile<PREC, NT, TH>(job, blockIdx.x * kWaveCols, blockIdx.y * TH, ftile, vtile, w1s,
+                            dyn + 16 * (size_t)job.T, reinterpret_cast<float2*>(dyn), true);
+  }
+}
+
+// Persistent form: workgroup b processes items b, b + gridDim.x, ... of a
+// cost-ordered list; item = (job index, tile x0, tile y0, -).  Dynamic LDS is
+// sized for T_max: cos/sin table first, then the per-harmonic tables.
+template <int PREC, int NT, int TH>
+__global__ void __launch_bounds__(kWaveThreads) wave_batched_kernel(const JobDesc* __restrict__ jobs,
+                                                                    const int4* __restrict__ items,
+                                                                    int n_items, int t_max) {
+  if constexpr (kWaveBuildable<PREC, NT, TH>) {
+    constexpr size_t TILE_ELEMS = WaveLds<PREC, NT, TH>::FROWS * WaveGeo<PREC, NT>::FW;
+    __shared__ __attribute__((aligned(16))) uint16_t ftile[TILE_ELEMS];
+    __shared__ __attribute__((aligned(16))) _Float16 vtile[WaveGeo<PREC, NT>::FP16 ? TILE_ELEMS : 8];
+    __shared__ float w1s[2 * BF_MAX_W + 1];
+    extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
+    float2* lut = reinterpret_cast<float2*>(dyn);
+    unsigned char* tab = dyn + 16 * (size_t)t_max;
+    int lut_t = -1;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+      const int4 w = items[it];
+      const JobDesc& job = jobs[w.x];
+      wave_tile<PREC, NT, TH>(job, w.y, w.z, ftile, vtile, w1s, tab, lut, job.T != lut_t);
+      lut_t = job.T;
+    }
   }
 }
 
@@ -297,6 +326,72 @@ hipError_t launch_wave(const JobDesc& job, hipStream_t stream) {
   dim3 grid((job.width + kWaveCols - 1) / kWaveCols, (job.height + TH - 1) / TH);
   hipLaunchKernelGGL((wave_kernel<PREC, NT, TH>), grid, dim3(kWaveThreads), wave_dynamic_lds(job.T), stream, job);
   return hipGetLastError();
+}
+
+// Geometry and kernel family of one job for the batched path.
+template <int PREC, int NT>
+TileChoice choose_tile(const JobDesc& job, int th_pref) {
+  const bool integer = (job.flags & BF_FLAG_INTEGER_INPUT) != 0;
+  if constexpr (PREC != BF_PLANES_FP32) {
+    if (integer) {
+      if (th_pref > 32 && wave_fits<PREC, NT, 64>(job.T)) return TileChoice{kWaveCols, 64, 1};
+      if (wave_fits<PREC, NT, 32>(job.T)) return TileChoice{kWaveCols, 32, 1};
+    }
+  } else if (integer) {
+    if (th_pref > 32 && staged_fits<PREC, NT, 64>(job.T)) return TileChoice{Geo<PREC, NT>::COLS, 64, 2};
+    if (staged_fits<PREC, NT, 32>(job.T)) return TileChoice{Geo<PREC, NT>::COLS, 32, 2};
+  }
+  return TileChoice{Geo<PREC, NT>::COLS, 32, 0};
+}
+
+// One persistent launch over `n_items` items of one (family, TH) class.
+template <int PREC, int NT>
+hipError_t launch_batched_class(const JobDesc* jobs, const int4* items, int n_items, int t_max,
+                                TileChoice tc, int grid, hipStream_t stream) {
+  if (n_items <= 0) return hipSuccess;
+  auto fit_grid = [&](const void* fn, int threads, size_t dyn) {
+    if (grid > 0) return min(grid, n_items);
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, dyn) != hipSuccess || per_cu < 1)
+      per_cu = 1;
+    return min(n_items, cus * per_cu);
+  };
+  if (tc.family == 1) {
+    if constexpr (PREC == BF_PLANES_FP32) return hipErrorInvalidValue;
+    const size_t dyn = wave_dynamic_lds(t_max);
+    if (tc.th == 64) {
+      if (!wave_fits<PREC, NT, 64>(t_max)) return hipErrorInvalidConfiguration;
+      const int g = fit_grid(reinterpret_cast<const void*>(&wave_batched_kernel<PREC, NT, 64>), kWaveThreads, dyn);
+      hipLaunchKernelGGL((wave_batched_kernel<PREC, NT, 64>), dim3(g), dim3(kWaveThreads), dyn, stream,
+                         jobs, items, n_items, t_max);
+    } else {
+      if (!wave_fits<PREC, NT, 32>(t_max)) return hipErrorInvalidConfiguration;
+      const int g = fit_grid(reinterpret_cast<const void*>(&wave_batched_kernel<PREC, NT, 32>), kWaveThreads, dyn);
+      hipLaunchKernelGGL((wave_batched_kernel<PREC, NT, 32>), dim3(g), dim3(kWaveThreads), dyn, stream,
+                         jobs, items, n_items, t_max);
+    }
+    return hipGetLastError();
+  }
+  const size_t dyn = dynamic_lds(t_max);
+  auto go = [&](auto th_c, auto int_c) -> hipError_t {
+    constexpr int TH = decltype(th_c)::value;
+    constexpr bool INT = decltype(int_c)::value;
+    constexpr bool staged = INT && Lds<PREC, NT, TH, true>::fits;
+    if (Lds<PREC, NT, TH, staged>::total + dyn > kLdsLimit) return hipErrorInvalidConfiguration;
+    const int g = fit_grid(reinterpret_cast<const void*>(&fused_batched_kernel<PREC, NT, TH, INT>),
+                           Geo<PREC, NT>::THREADS, dyn);
+    hipLaunchKernelGGL((fused_batched_kernel<PREC, NT, TH, INT>), dim3(g), dim3(Geo<PREC, NT>::THREADS), dyn,
+                       stream, jobs, items, n_items, t_max);
+    return hipGetLastError();
+  };
+  if (tc.family == 2) {
+    return tc.th == 64 ? go(std::integral_constant<int, 64>{}, std::true_type{})
+                       : go(std::integral_constant<int, 32>{}, std::true_type{});
+  }
+  return go(std::integral_constant<int, 32>{}, std::false_type{});
 }
 
 }  // namespace fused_detail

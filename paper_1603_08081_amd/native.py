@@ -85,6 +85,16 @@ def _load():
     lib.bf_filter.restype = I
     lib.bf_filter_batched.argtypes = [jp, I, I, P, Z, P]
     lib.bf_filter_batched.restype = I
+    lib.bf_plan_create.argtypes = [jp, I, I, ctypes.POINTER(P)]
+    lib.bf_plan_create.restype = I
+    lib.bf_plan_workspace_bytes.argtypes = [P]
+    lib.bf_plan_workspace_bytes.restype = Z
+    lib.bf_plan_upload.argtypes = [P, P, Z, P]
+    lib.bf_plan_upload.restype = I
+    lib.bf_plan_launch.argtypes = [P, P, I]
+    lib.bf_plan_launch.restype = I
+    lib.bf_plan_destroy.argtypes = [P]
+    lib.bf_plan_destroy.restype = None
     lib.bf_last_error.argtypes = []
     lib.bf_last_error.restype = ctypes.c_char_p
     hip = sorted(p for p in _hip_runtimes() if "libamdhip64" in p)
@@ -204,3 +214,39 @@ def bf_filter_batched(jobs: Sequence[Job], prec: str = "fp32", workspace=None, w
     arr = (bf_job * len(jobs))(*[j.struct for j in jobs])
     return _check(lib.bf_filter_batched(arr, len(jobs), PLANES[prec], _ptr(workspace), int(ws_bytes),
                                         _stream_handle(stream)))
+
+
+class Plan:
+    """bf_plan_create / _upload / _launch / _destroy (include/bf.h).
+
+    Holds the opaque plan handle and the Job objects whose host arrays it was
+    built from; the jobs' device buffers must outlive the plan's launches.
+    """
+
+    def __init__(self, jobs: Sequence[Job], prec: str = "fp32"):
+        self.jobs = list(jobs)
+        self.prec = prec
+        self.handle = ctypes.c_void_p()
+        arr = (bf_job * len(self.jobs))(*[j.struct for j in self.jobs])
+        self.status = _check(lib.bf_plan_create(arr, len(self.jobs), PLANES[prec], ctypes.byref(self.handle)))
+
+    def workspace_bytes(self) -> int:
+        return int(lib.bf_plan_workspace_bytes(self.handle))
+
+    def upload(self, workspace, ws_bytes: int, stream=None) -> int:
+        self._ws = workspace  # keep the tensor alive while the plan points at it
+        return _check(lib.bf_plan_upload(self.handle, _ptr(workspace), int(ws_bytes), _stream_handle(stream)))
+
+    def launch(self, stream=None, use_graph: bool = False) -> int:
+        return _check(lib.bf_plan_launch(self.handle, _stream_handle(stream), 1 if use_graph else 0))
+
+    def destroy(self):
+        if self.handle:
+            lib.bf_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

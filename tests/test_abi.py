@@ -137,3 +137,49 @@ def test_unknown_precision_rejected():
 def test_workspace_query_for_valid_jobs():
     assert native.bf_workspace_bytes([_job()], "fp32") >= 0
     assert native.bf_workspace_bytes([_job(), _job(W=-1, sigma_s=2.0)], "fp16") >= 0
+
+
+def test_batched_workspace_grows_with_jobs_and_tiles():
+    one = native.bf_workspace_bytes([_job()], "fp16")
+    two = native.bf_workspace_bytes([_job(), _job()], "fp16")
+    assert 0 < one < two
+    big = native.bf_workspace_bytes([_job(height=2000, width=3000, src_pitch=3000, dst_pitch=3000,
+                                          dst=FAKE_DST + (1 << 26))], "fp16")
+    assert big > one
+    # the table holds one 16-byte work item per output tile
+    assert (big - one) % 16 == 0
+
+
+def test_plan_host_side_without_device_work():
+    pl = native.Plan([_job(), _job(W=-1, sigma_s=2.0)], "fp16")
+    assert pl.status == native.BF_OK
+    assert pl.workspace_bytes() == native.bf_workspace_bytes(pl.jobs, "fp16")
+    # launch before upload, and uploads into a missing or small workspace, fail before any HIP call
+    with pytest.raises(native.BfError) as ei:
+        pl.launch(stream=0)
+    assert ei.value.code == native.BF_E_INVALID
+    with pytest.raises(native.BfError) as ei:
+        pl.upload(None, 0, stream=0)
+    assert ei.value.code == native.BF_E_WORKSPACE
+    with pytest.raises(native.BfError) as ei:
+        pl.upload(0x30000000, pl.workspace_bytes() - 1, stream=0)
+    assert ei.value.code == native.BF_E_WORKSPACE
+    with pytest.raises(native.BfError) as ei:
+        pl.upload(0x30000008, pl.workspace_bytes(), stream=0)   # misaligned
+    assert ei.value.code == native.BF_E_WORKSPACE
+    pl.destroy()
+    native.lib.bf_plan_destroy(None)
+
+
+def test_plan_reports_unconverged_fit_and_rejects_bad_jobs():
+    pl = native.Plan([_job(d=None, range_kind="exponential", sigma_r=20.0, eps=1e-2, K_max=24)], "fp32")
+    assert pl.status == native.BF_FIT_NOT_CONVERGED
+    pl.destroy()
+    with pytest.raises(native.BfError) as ei:
+        native.Plan([_job(), _job(T=0)], "fp32")
+    assert ei.value.code == native.BF_E_INVALID
+    assert "job 1" in native.bf_last_error()
+    out = ctypes.c_void_p(1)
+    assert native.lib.bf_plan_create(None, 0, 0, ctypes.byref(out)) == native.BF_E_INVALID
+    assert out.value is None
+    assert native.lib.bf_plan_workspace_bytes(None) == ctypes.c_size_t(-1).value

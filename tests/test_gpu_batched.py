@@ -1,0 +1,256 @@
+"""GPU tests of the batched path (bf_filter_batched and plans) through the C ABI.
+
+- Batched output equals the single-image entry point bit for bit (same kernel
+  family and per-tile arithmetic; only the schedule differs), for every plane
+  format, on a mix of sizes, windows, range kernels, T and K.
+- Every grid mode (persistent grid sized by occupancy, one workgroup per tile,
+  a tiny grid that makes each workgroup walk many tiles of different jobs and
+  T) gives the same bits.
+- Plans: eager launch and HIP-graph replay equal bf_filter_batched, on every
+  replay, with other device work between replays and new input written into
+  the same buffers.
+- The mixed 64-image workload (sizes 256..4096 per side, W 6..48, K up to 40,
+  Gaussian and exponential range kernels) in FP32 planes against the FP64
+  oracle of eq. (9) on sampled rows of every image.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import WORKLOADS, batch_specs, polygon_image, workload_images
+from tests.gpu_util import pixels_of_rows, sample_rows
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-3
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _mixed_specs():
+    """Small jobs covering the kernel classes: ragged sizes, several window
+    classes, box and Gaussian windows, both range kernels, T != 255, K = 0,
+    integer and non-integer inputs."""
+    return [
+        dict(h=45, w=77, spatial="gaussian", sigma_s=1.0, W=3, rk="gaussian", sr=20.0, T=255, eps=1e-3, integer=True),
+        dict(h=130, w=200, spatial="gaussian", sigma_s=3.0, W=9, rk="exponential", sr=20.0, T=255, eps=1e-2,
+             integer=True),
+        dict(h=97, w=131, spatial="box", sigma_s=1.0, W=15, rk="gaussian", sr=30.0, T=255, eps=1e-3, integer=True),
+        dict(h=300, w=257, spatial="gaussian", sigma_s=8.0, W=24, rk="gaussian", sr=15.0, T=255, eps=0.0, K_max=32,
+             integer=True),
+        dict(h=120, w=140, spatial="gaussian", sigma_s=10.0, W=30, rk="gaussian", sr=40.0, T=100, eps=1e-3,
+             integer=True),
+        dict(h=64, w=90, spatial="gaussian", sigma_s=4.0, W=12, rk="gaussian", sr=500.0, T=255, eps=0.5, integer=True),
+        dict(h=111, w=99, spatial="gaussian", sigma_s=5.0, W=15, rk="gaussian", sr=25.0, T=255, eps=1e-3,
+             integer=False),
+        dict(h=150, w=141, spatial="gaussian", sigma_s=16.0, W=48, rk="exponential", sr=60.0, T=255, eps=1e-2,
+             integer=True),
+        dict(h=70, w=260, spatial="gaussian", sigma_s=2.0, W=6, rk="gaussian", sr=10.0, T=31, eps=1e-4, integer=True),
+    ]
+
+
+def _inputs(specs):
+    imgs = []
+    for i, s in enumerate(specs):
+        f = polygon_image(s["h"], s["w"], seed=7000 + i)
+        f = np.clip(f, 0, s["T"])
+        if not s["integer"]:
+            f = f + np.random.default_rng(i).uniform(-0.4, 0.4, f.shape).astype(np.float32)
+            f = np.clip(f, 0, s["T"]).astype(np.float32)
+        imgs.append(f.astype(np.float32))
+    return imgs
+
+
+def _jobs(native, specs, srcs, dsts):
+    out = []
+    for s, x, y in zip(specs, srcs, dsts):
+        out.append(native.Job(x, y, spatial=s["spatial"], sigma_s=s["sigma_s"], W=s["W"], range_kind=s["rk"],
+                              sigma_r=s["sr"], T=s["T"], eps=s["eps"], K_max=s.get("K_max", min(40, s["T"])),
+                              integer_input=s["integer"]))
+    return out
+
+
+def _batched(native, torch, jobs, prec, stream):
+    n = native.bf_workspace_bytes(jobs, prec)
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+    st = native.bf_filter_batched(jobs, prec, ws, n, stream)
+    return ws, st
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_batched_equals_single_bitwise(prec):
+    torch = _torch()
+    from paper_1603_08081_amd import native
+    specs = _mixed_specs()
+    imgs = _inputs(specs)
+    srcs = [torch.from_numpy(f).cuda() for f in imgs]
+    d_single = [torch.full_like(x, -1.0) for x in srcs]
+    d_batch = [torch.full_like(x, -1.0) for x in srcs]
+    stream = torch.cuda.current_stream()
+    for j in _jobs(native, specs, srcs, d_single):
+        native.bf_filter(j, prec, stream=stream)
+    jobs = _jobs(native, specs, srcs, d_batch)
+    ws, st = _batched(native, torch, jobs, prec, stream)
+    torch.cuda.synchronize()
+    assert st in (native.BF_OK, native.BF_FIT_NOT_CONVERGED)
+    for i, (a, b) in enumerate(zip(d_single, d_batch)):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        print("job %d %s: max |single - batched| = %.3g" % (i, specs[i], np.abs(a - b).max()), flush=True)
+        assert np.isfinite(b).all()
+        assert np.array_equal(a, b), "job %d" % i
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+@pytest.mark.parametrize("grid", ["", "items", "3", "1"])
+def test_grid_modes_agree(prec, grid, monkeypatch):
+    torch = _torch()
+    from paper_1603_08081_amd import native
+    specs = _mixed_specs()
+    imgs = _inputs(specs)
+    srcs = [torch.from_numpy(f).cuda() for f in imgs]
+    ref = [torch.full_like(x, -1.0) for x in srcs]
+    out = [torch.full_like(x, -1.0) for x in srcs]
+    stream = torch.cuda.current_stream()
+    for j in _jobs(native, specs, srcs, ref):
+        native.bf_filter(j, prec, stream=stream)
+    monkeypatch.setenv("BF_BATCH_GRID", grid)
+    jobs = _jobs(native, specs, srcs, out)
+    ws, _ = _batched(native, torch, jobs, prec, stream)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(ref, out)):
+        assert torch.equal(a, b), "grid %r job %d" % (grid, i)
+
+
+def test_plan_eager_and_graph_replays():
+    torch = _torch()
+    from paper_1603_08081_amd import native
+    specs = _mixed_specs()
+    imgs = _inputs(specs)
+    srcs = [torch.from_numpy(f).cuda() for f in imgs]
+    ref = [torch.full_like(x, -1.0) for x in srcs]
+    out = [torch.full_like(x, -1.0) for x in srcs]
+    stream = torch.cuda.current_stream()
+    prec = "fp16"
+    jref = _jobs(native, specs, srcs, ref)
+    ws_ref, _ = _batched(native, torch, jref, prec, stream)
+
+    plan = native.Plan(_jobs(native, specs, srcs, out), prec)
+    ws = torch.empty(plan.workspace_bytes(), dtype=torch.uint8, device="cuda")
+    plan.upload(ws, plan.workspace_bytes(), stream)
+    plan.launch(stream, use_graph=False)
+    torch.cuda.synchronize()
+    for a, b in zip(ref, out):
+        assert torch.equal(a, b)
+    for rep in range(4):
+        for o in out:
+            o.fill_(-7.0)            # other device work between replays
+        torch.cuda.synchronize()
+        plan.launch(stream, use_graph=True)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(ref, out)):
+            assert torch.equal(a, b), "replay %d job %d" % (rep, i)
+    # new input in the same buffers: the replay filters it
+    for i, x in enumerate(srcs):
+        x.copy_(torch.flip(x, dims=[1]))
+    native.bf_filter_batched(jref, prec, ws_ref, ws_ref.numel(), stream)
+    plan.launch(stream, use_graph=True)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(ref, out)):
+        assert torch.equal(a, b), "new input, job %d" % i
+    plan.destroy()
+
+
+def test_plan_on_side_stream_and_reupload():
+    torch = _torch()
+    from paper_1603_08081_amd import native
+    specs = _mixed_specs()[:4]
+    imgs = _inputs(specs)
+    srcs = [torch.from_numpy(f).cuda() for f in imgs]
+    ref = [torch.full_like(x, -1.0) for x in srcs]
+    out = [torch.full_like(x, -1.0) for x in srcs]
+    for j in _jobs(native, specs, srcs, ref):
+        native.bf_filter(j, "fp32", stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    plan = native.Plan(_jobs(native, specs, srcs, out), "fp32")
+    n = plan.workspace_bytes()
+    ws1 = torch.empty(n, dtype=torch.uint8, device="cuda")
+    ws2 = torch.empty(n + 4096, dtype=torch.uint8, device="cuda")
+    with torch.cuda.stream(side):
+        plan.upload(ws1, n, side)
+        plan.launch(side, use_graph=True)
+        plan.upload(ws2, n + 4096, side)      # rebinding drops the old graph
+        for o in out:
+            o.fill_(0.0)
+        plan.launch(side, use_graph=True)
+    side.synchronize()
+    for a, b in zip(ref, out):
+        assert torch.equal(a, b)
+    plan.destroy()
+
+
+@pytest.fixture(scope="module")
+def batch64():
+    specs = batch_specs(WORKLOADS["batch64_mixed"]["n"], WORKLOADS["batch64_mixed"]["seed"])
+    imgs = workload_images("batch64_mixed")
+    return specs, imgs
+
+
+def test_batch64_mixed_fp32_vs_oracle(batch64):
+    torch = _torch()
+    from paper_1603_08081_amd import native
+    specs, imgs = batch64
+    wl = WORKLOADS["batch64_mixed"]
+    srcs = [torch.from_numpy(f).cuda() for f in imgs]
+    dsts = [torch.full_like(x, -1.0) for x in srcs]
+    fits = {}
+    jobs = []
+    for s, x, y in zip(specs, srcs, dsts):
+        key = (s["range_kind"], s["sigma_r"])
+        fits[key] = oracle.fit_kernel(s["range_kind"], s["sigma_r"], wl["T"], wl["eps"], wl["K_max"])
+        jobs.append(native.Job(x, y, spatial="gaussian", sigma_s=s["sigma_s"], W=s["W"],
+                               range_kind=s["range_kind"], sigma_r=s["sigma_r"], T=wl["T"], eps=wl["eps"],
+                               K_max=wl["K_max"], integer_input=True))
+    ws, st = _batched(native, torch, jobs, "fp32", torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i, (s, f) in enumerate(zip(specs, imgs)):
+        H, Wd = f.shape
+        out = dsts[i].cpu().numpy()
+        assert np.isfinite(out).all()
+        rows = sample_rows(H, Wd, s["W"], n_random=4, seed=i)
+        pix = pixels_of_rows(rows, Wd)
+        r = fits[(s["range_kind"], s["sigma_r"])]
+        ref = oracle.fourier(f, "gaussian", s["sigma_s"], s["W"], r.d, wl["T"], pixels=pix)
+        err = np.abs(out.ravel()[pix] - ref).max()
+        worst = max(worst, err)
+        assert err <= TOL_FP32, "image %d (%dx%d, W=%d, K=%d): %.3g" % (i, H, Wd, s["W"], r.K, err)
+    print("batch64 fp32: worst sampled error vs eq. (9) FP64 = %.3e" % worst, flush=True)
+
+
+def test_batch64_mixed_fp16_vs_oracle(batch64):
+    torch = _torch()
+    from paper_1603_08081_amd import native
+    specs, imgs = batch64
+    wl = WORKLOADS["batch64_mixed"]
+    srcs = [torch.from_numpy(f).cuda() for f in imgs]
+    dsts = [torch.full_like(x, -1.0) for x in srcs]
+    jobs = [native.Job(x, y, spatial="gaussian", sigma_s=s["sigma_s"], W=s["W"], range_kind=s["range_kind"],
+                       sigma_r=s["sigma_r"], T=wl["T"], eps=wl["eps"], K_max=wl["K_max"], integer_input=True)
+            for s, x, y in zip(specs, srcs, dsts)]
+    ws, st = _batched(native, torch, jobs, "fp16", torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i, (s, f) in enumerate(zip(specs, imgs[:16])):
+        H, Wd = f.shape
+        out = dsts[i].cpu().numpy()
+        rows = sample_rows(H, Wd, s["W"], n_random=2, seed=i)
+        pix = pixels_of_rows(rows, Wd)
+        r = oracle.fit_kernel(s["range_kind"], s["sigma_r"], wl["T"], wl["eps"], wl["K_max"])
+        ref = oracle.fourier(f, "gaussian", s["sigma_s"], s["W"], r.d, wl["T"], pixels=pix)
+        worst = max(worst, np.abs(out.ravel()[pix] - ref).max())
+    print("batch64 fp16: worst sampled error vs eq. (9) FP64 = %.3e" % worst, flush=True)
+    assert worst < 0.5
