@@ -41,6 +41,41 @@ def alg_flops_per_px(K, W):
     return (4 * K + 1) * 2 * (2 * W + 1) * 2
 
 
+def kernel_sources_digest():
+    """sha256 over the library's kernel and host sources (byte counters taken
+    on other sources no longer describe the kernel)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1603_08081_amd", "csrc")
+    h = hashlib.sha256()
+    for fn in sorted(os.listdir(csrc)):
+        if fn.endswith((".h", ".hip", ".cpp")):
+            h.update(fn.encode())
+            with open(os.path.join(csrc, fn), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, prec, frames):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE runs scaled by a copy of known size);
+    None when there is none for this workload or the sources have changed
+    since the counters were taken."""
+    name = "%s_%s_%s.md" % ("wave_batched_kernel" if prec != "fp32" else "fused_batched_kernel", workload, prec)
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for ln in fh:
+            if ":" in ln and ln.lstrip("- ").split(":")[0].strip() in (
+                    "traffic_bytes_per_launch", "sources_sha256", "frames"):
+                k, v = ln.lstrip("- ").split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("sources_sha256") != kernel_sources_digest() or int(vals.get("frames", -1)) != frames:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,6 +91,11 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the error check against the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--eager", action="store_true",
+                    help="launch the plan eagerly instead of replaying its HIP graph")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after timing, run one plain elementwise copy (negation) of this many MiB of "
+                         "float32, the known-size reference for HBM byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -128,7 +168,7 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
 
-    ms = timed(args.precision, dst, args.steps, args.warmup)
+    ms = timed(args.precision, dst, args.steps, args.warmup, use_graph=not args.eager)
     px = n * H * Wd
     value = px / (ms * 1e-3) / 1e6
     log("%s planes: %.3f ms/step, %.1f Mpix/s (plan, graph replay)" % (args.precision, ms, value))
@@ -156,6 +196,14 @@ def main():
     else:
         dst32 = dst if args.precision == "fp32" else None
 
+    if args.calib_copy_mib > 0:
+        a = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        log("calibration copy: %d MiB read + %d MiB written" % (args.calib_copy_mib, args.calib_copy_mib))
+        del a, b
+
     # ---- roofline of the dominant kernel: every frame has the same window and
     # K, so the plan is one persistent launch per step
     launches = 1
@@ -164,7 +212,8 @@ def main():
     achieved = flops / avg_launch_s / 1e12
     peak = PEAK_TFLOPS[args.precision]
     roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
+            "frac": round(achieved / peak, 4),
+            "traffic": measured_traffic(args.workload, args.precision, n),
             "kernel": ("wave_batched_kernel" if args.precision != "fp32" else "fused_batched_kernel") +
                       " (modulate + row/column MFMA Toeplitz + demodulate + divide)",
             "alg_flops_per_px": alg_flops_per_px(K, W), "launches_per_step": launches}
