@@ -67,6 +67,14 @@ int grid_mode_from_env() {
   return v > 0 ? v : 0;
 }
 
+// Preferred output-tile height (32 or 64 rows) from BF_TILE_ROWS; 0 = default.
+int tile_rows_from_env() {
+  const char* s = std::getenv("BF_TILE_ROWS");
+  if (!s || !*s) return 0;
+  const int v = std::atoi(s);
+  return (v == 32 || v == 64) ? v : 0;
+}
+
 int valid_prec(bf_planes prec) {
   return prec == BF_PLANES_FP32 || prec == BF_PLANES_FP16 || prec == BF_PLANES_BF16;
 }
@@ -77,6 +85,7 @@ int build_plan(const bf_job* jobs, int n_jobs, bf_planes prec, PlanData& p) {
   p = PlanData{};
   p.prec = prec;
   p.grid = grid_mode_from_env();
+  const int th_env = tile_rows_from_env();
   p.descs.resize(n_jobs);
   std::vector<TileChoice> choice(n_jobs);
   std::map<long, std::vector<int>> by_class;  // key (nt, family, th) -> jobs
@@ -91,7 +100,7 @@ int build_plan(const bf_job* jobs, int n_jobs, bf_planes prec, PlanData& p) {
     p.descs[i] = r.desc;
     const int nt = window_tiles(r.desc.W);
     // fp32 planes with wide windows need too many registers for 64-row tiles
-    const int th_pref = (prec == BF_PLANES_FP32 && nt >= 5) ? 32 : 64;
+    const int th_pref = th_env ? th_env : (prec == BF_PLANES_FP32 && nt >= 5) ? 32 : 64;
     choice[i] = choose_tile(r.desc, prec, th_pref);
     const long key = (long)nt * 10000 + choice[i].family * 1000 + choice[i].th;
     by_class[key].push_back(i);

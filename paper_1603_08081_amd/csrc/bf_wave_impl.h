@@ -28,9 +28,22 @@ constexpr int kWaveNW = 8;                       // waves per workgroup
 constexpr int kWaveThreads = 64 * kWaveNW;
 constexpr int kWaveCols = 16 * kWaveNW;          // output columns per tile
 
+// float16 planes can take (f - c0) cos / sin from packed fp16 multiplies
+// against a staged (f - c0) tile (1) or from 8-byte tables like bfloat16 (0);
+// the tables need half the LDS per tile.
+#ifndef BF_WAVE_PKMUL
+#define BF_WAVE_PKMUL 1
+#endif
+// optional register budget of the wave kernels (waves per SIMD)
+#ifdef BF_WAVE_MIN_WAVES
+#define BF_WAVE_OCC __attribute__((amdgpu_waves_per_eu(BF_WAVE_MIN_WAVES)))
+#else
+#define BF_WAVE_OCC
+#endif
+
 template <int PREC, int NT>
 struct WaveGeo {
-  static constexpr bool FP16 = (PREC == BF_PLANES_FP16);
+  static constexpr bool FP16 = (PREC == BF_PLANES_FP16) && BF_WAVE_PKMUL;
   static constexpr int KS = (NT + 1) / 2;
   static constexpr int LWU = 16 * (kWaveNW - 1) + 32 * KS;  // staged input columns
   static constexpr int FW = LWU + 8;                         // padded row (u16 / fp16)
@@ -279,7 +292,7 @@ constexpr bool kWaveBuildable =
     PREC != BF_PLANES_FP32 && WaveLds<PREC, NT, TH>::total + 32 * 256 + 16 * 255 <= kLdsLimit;
 
 template <int PREC, int NT, int TH>
-__global__ void __launch_bounds__(kWaveThreads) wave_kernel(const JobDesc job) {
+__global__ void __launch_bounds__(kWaveThreads) BF_WAVE_OCC wave_kernel(const JobDesc job) {
   if constexpr (kWaveBuildable<PREC, NT, TH>) {
     constexpr size_t TILE_ELEMS = WaveLds<PREC, NT, TH>::FROWS * WaveGeo<PREC, NT>::FW;
     __shared__ __attribute__((aligned(16))) uint16_t ftile[TILE_ELEMS];
@@ -295,7 +308,7 @@ __global__ void __launch_bounds__(kWaveThreads) wave_kernel(const JobDesc job) {
 // cost-ordered list; item = (job index, tile x0, tile y0, -).  Dynamic LDS is
 // sized for T_max: cos/sin table first, then the per-harmonic tables.
 template <int PREC, int NT, int TH>
-__global__ void __launch_bounds__(kWaveThreads) wave_batched_kernel(const JobDesc* __restrict__ jobs,
+__global__ void __launch_bounds__(kWaveThreads) BF_WAVE_OCC wave_batched_kernel(const JobDesc* __restrict__ jobs,
                                                                     const int4* __restrict__ items,
                                                                     int n_items, int t_max) {
   if constexpr (kWaveBuildable<PREC, NT, TH>) {
