@@ -80,7 +80,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp16", choices=["bf16", "fp16", "fp32"],
                     help="plane format of the headline number (fp16 meets the 0.5 gray-level bar "
                          "on this workload; bf16 is timed and checked alongside)")

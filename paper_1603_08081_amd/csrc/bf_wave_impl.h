@@ -24,6 +24,16 @@ namespace fused_detail {
 
 typedef _Float16 h2v __attribute__((ext_vector_type(2)));
 
+// (low 16 bits of a) | (low 16 bits of b) << 16, and the same for the high
+// halves: one byte permute each (v_perm_b32 takes its second source as
+// bytes 0-3 and its first as bytes 4-7)
+__device__ __forceinline__ uint32_t lo_halves(uint32_t a, uint32_t b) {
+  return __builtin_amdgcn_perm(b, a, 0x05040100u);
+}
+__device__ __forceinline__ uint32_t hi_halves(uint32_t a, uint32_t b) {
+  return __builtin_amdgcn_perm(b, a, 0x07060302u);
+}
+
 constexpr int kWaveNW = 8;                       // waves per workgroup
 constexpr int kWaveThreads = 64 * kWaveNW;
 constexpr int kWaveCols = 16 * kWaveNW;          // output columns per tile
@@ -32,7 +42,12 @@ constexpr int kWaveCols = 16 * kWaveNW;          // output columns per tile
 // against a staged (f - c0) tile (1) or from 8-byte tables like bfloat16 (0);
 // the tables need half the LDS per tile.
 #ifndef BF_WAVE_PKMUL
-#define BF_WAVE_PKMUL 1
+#define BF_WAVE_PKMUL 0
+#endif
+// registers (per lane) the wave kernel may spend on keeping the staged
+// row-pass operands of a whole tile across harmonics
+#ifndef BF_WAVE_HOIST_REGS
+#define BF_WAVE_HOIST_REGS 0
 #endif
 // optional register budget of the wave kernels (waves per SIMD)
 #ifdef BF_WAVE_MIN_WAVES
@@ -153,6 +168,24 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
   // demodulation table offset of gray level f from its modulation offset
   auto dem_off = [](uint32_t off) { return FP16 ? off * 2 : off; };
 
+  // The staged tile does not change across harmonics: when the operands of
+  // all row-pass steps fit the register budget, read them from LDS once.
+  constexpr bool HOIST = NS * KS * (FP16 ? 8 : 4) <= BF_WAVE_HOIST_REGS;
+  constexpr int HS = HOIST ? NS : 1, HK = HOIST ? KS : 1, HV = (HOIST && FP16) ? NS : 1;
+  uint4 fq_h[HS][HK], vq_h[HV][HK];
+  if constexpr (HOIST) {
+#pragma unroll
+    for (int s2 = 0; s2 < NS; ++s2)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int rr = 16 * s2 + n16, cc = 16 * wave + 32 * ks + 8 * g;
+        fq_h[s2][ks] = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
+        if constexpr (FP16) vq_h[s2][ks] = *reinterpret_cast<const uint4*>(&vtile[rr][cc]);
+      }
+  }
+  (void)fq_h;
+  (void)vq_h;
+
   build(0);
   if (K >= 1) build(1);
   for (int k = 0; k <= K; ++k) {
@@ -175,11 +208,15 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
           typename PT::V8 a;
           uint32_t vq[4];
           if constexpr (FP16) {
-            const uint4 v4 = *reinterpret_cast<const uint4*>(&vtile[rr][cc]);
+            uint4 v4;
+            if constexpr (HOIST) v4 = vq_h[s][ks];
+            else v4 = *reinterpret_cast<const uint4*>(&vtile[rr][cc]);
             vq[0] = v4.x; vq[1] = v4.y; vq[2] = v4.z; vq[3] = v4.w;
           }
           if constexpr (NPL == 4) {
-            const uint4 fq = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
+            uint4 fq;
+            if constexpr (HOIST) fq = fq_h[s][ks];
+            else fq = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
             const uint32_t fw[4] = {fq.x, fq.y, fq.z, fq.w};
             uint32_t pc[4], ps[4], pfc[4], pfs[4];
 #pragma unroll
@@ -187,18 +224,18 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
               if constexpr (FP16) {
                 const uint32_t ta = *reinterpret_cast<const uint32_t*>(tm + (fw[h] & 0xffffu));
                 const uint32_t tb = *reinterpret_cast<const uint32_t*>(tm + (fw[h] >> 16));
-                pc[h] = (ta & 0xffffu) | (tb << 16);
-                ps[h] = (ta >> 16) | (tb & 0xffff0000u);
+                pc[h] = lo_halves(ta, tb);
+                ps[h] = hi_halves(ta, tb);
                 const h2v vv = __builtin_bit_cast(h2v, vq[h]);
                 pfc[h] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(h2v, pc[h]) * vv);
                 pfs[h] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(h2v, ps[h]) * vv);
               } else {
                 const uint2 ta = *reinterpret_cast<const uint2*>(tm + (fw[h] & 0xffffu));
                 const uint2 tb = *reinterpret_cast<const uint2*>(tm + (fw[h] >> 16));
-                pc[h] = (ta.x & 0xffffu) | (tb.x << 16);
-                ps[h] = (ta.x >> 16) | (tb.x & 0xffff0000u);
-                pfc[h] = (ta.y & 0xffffu) | (tb.y << 16);
-                pfs[h] = (ta.y >> 16) | (tb.y & 0xffff0000u);
+                pc[h] = lo_halves(ta.x, tb.x);
+                ps[h] = hi_halves(ta.x, tb.x);
+                pfc[h] = lo_halves(ta.y, tb.y);
+                pfs[h] = hi_halves(ta.y, tb.y);
               }
             }
             __builtin_memcpy(&a, pc, 16);
@@ -214,7 +251,9 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
             if constexpr (FP16) {
               __builtin_memcpy(&a, vq, 16);
             } else {
-              const uint4 fq = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
+              uint4 fq;
+              if constexpr (HOIST) fq = fq_h[s][ks];
+              else fq = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
               const uint32_t fw[4] = {fq.x, fq.y, fq.z, fq.w};
               uint32_t pv[4];
 #pragma unroll
