@@ -123,9 +123,9 @@ int resolve_job(const bf_job* j, Resolved* out) {
 int pick_tile_rows(const JobDesc& jd, bf_planes prec) {
   // fp32 planes with wide windows need too many registers for 64-row tiles
   if (prec == BF_PLANES_FP32 && window_tiles(jd.W) >= 5) return 32;
+  // 64-row tiles once every CU gets two workgroups or more
   const long col_blocks = (jd.width + tile_cols(prec) - 1) / tile_cols(prec);
-  const long blocks64 = col_blocks * ((jd.height + 63) / 64);
-  return blocks64 >= 512 ? 64 : 32;
+  return col_blocks * ((jd.height + 63) / 64) >= 512 ? 64 : 32;
 }
 
 }  // namespace bf

@@ -67,12 +67,12 @@ int grid_mode_from_env() {
   return v > 0 ? v : 0;
 }
 
-// Preferred output-tile height (32 or 64 rows) from BF_TILE_ROWS; 0 = default.
+// Preferred output-tile height (32, 64 or 128 rows) from BF_TILE_ROWS; 0 = default.
 int tile_rows_from_env() {
   const char* s = std::getenv("BF_TILE_ROWS");
   if (!s || !*s) return 0;
   const int v = std::atoi(s);
-  return (v == 32 || v == 64) ? v : 0;
+  return (v == 32 || v == 64 || v == 128) ? v : 0;
 }
 
 int valid_prec(bf_planes prec) {

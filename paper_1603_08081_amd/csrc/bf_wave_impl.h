@@ -34,7 +34,10 @@ __device__ __forceinline__ uint32_t hi_halves(uint32_t a, uint32_t b) {
   return __builtin_amdgcn_perm(b, a, 0x07060302u);
 }
 
-constexpr int kWaveNW = 8;                       // waves per workgroup
+#ifndef BF_WAVE_NW
+#define BF_WAVE_NW 8
+#endif
+constexpr int kWaveNW = BF_WAVE_NW;              // waves per workgroup
 constexpr int kWaveThreads = 64 * kWaveNW;
 constexpr int kWaveCols = 16 * kWaveNW;          // output columns per tile
 
@@ -380,17 +383,42 @@ hipError_t launch_wave(const JobDesc& job, hipStream_t stream) {
   return hipGetLastError();
 }
 
-// Geometry and kernel family of one job for the batched path.
+// 128-row tiles keep their P, Q accumulators in registers without spilling
+// only for the narrower window classes
+template <int NT>
+constexpr bool kWaveTall = NT <= 4;
+
+template <int PREC, int NT, int TH>
+bool wave_ok(int T) {
+  if constexpr (TH == 128 && !kWaveTall<NT>) return false;
+  else return wave_fits<PREC, NT, TH>(T);
+}
+
+// Calls fn(integral_constant<int, TH>) for a wave-kernel tile height.
+template <int NT, class F>
+hipError_t with_wave_rows(int th, F&& fn) {
+  if constexpr (kWaveTall<NT>) {
+    if (th == 128) return fn(std::integral_constant<int, 128>{});
+  }
+  if (th == 64) return fn(std::integral_constant<int, 64>{});
+  if (th == 32) return fn(std::integral_constant<int, 32>{});
+  return hipErrorInvalidValue;
+}
+
+// Geometry and kernel family of one job: 16-bit planes on integer gray levels
+// take the wave kernel with the tallest tile (<= th_pref) that fits; fp32
+// planes the shared-plane kernel with a staged tile; the rest the general path.
 template <int PREC, int NT>
 TileChoice choose_tile(const JobDesc& job, int th_pref) {
   const bool integer = (job.flags & BF_FLAG_INTEGER_INPUT) != 0;
   if constexpr (PREC != BF_PLANES_FP32) {
     if (integer) {
-      if (th_pref > 32 && wave_fits<PREC, NT, 64>(job.T)) return TileChoice{kWaveCols, 64, 1};
-      if (wave_fits<PREC, NT, 32>(job.T)) return TileChoice{kWaveCols, 32, 1};
+      if (th_pref >= 128 && wave_ok<PREC, NT, 128>(job.T)) return TileChoice{kWaveCols, 128, 1};
+      if (th_pref >= 64 && wave_ok<PREC, NT, 64>(job.T)) return TileChoice{kWaveCols, 64, 1};
+      if (wave_ok<PREC, NT, 32>(job.T)) return TileChoice{kWaveCols, 32, 1};
     }
   } else if (integer) {
-    if (th_pref > 32 && staged_fits<PREC, NT, 64>(job.T)) return TileChoice{Geo<PREC, NT>::COLS, 64, 2};
+    if (th_pref >= 64 && staged_fits<PREC, NT, 64>(job.T)) return TileChoice{Geo<PREC, NT>::COLS, 64, 2};
     if (staged_fits<PREC, NT, 32>(job.T)) return TileChoice{Geo<PREC, NT>::COLS, 32, 2};
   }
   return TileChoice{Geo<PREC, NT>::COLS, 32, 0};
@@ -412,20 +440,19 @@ hipError_t launch_batched_class(const JobDesc* jobs, const int4* items, int n_it
     return min(n_items, cus * per_cu);
   };
   if (tc.family == 1) {
-    if constexpr (PREC == BF_PLANES_FP32) return hipErrorInvalidValue;
-    const size_t dyn = wave_dynamic_lds(t_max);
-    if (tc.th == 64) {
-      if (!wave_fits<PREC, NT, 64>(t_max)) return hipErrorInvalidConfiguration;
-      const int g = fit_grid(reinterpret_cast<const void*>(&wave_batched_kernel<PREC, NT, 64>), kWaveThreads, dyn);
-      hipLaunchKernelGGL((wave_batched_kernel<PREC, NT, 64>), dim3(g), dim3(kWaveThreads), dyn, stream,
-                         jobs, items, n_items, t_max);
+    if constexpr (PREC == BF_PLANES_FP32) {
+      return hipErrorInvalidValue;
     } else {
-      if (!wave_fits<PREC, NT, 32>(t_max)) return hipErrorInvalidConfiguration;
-      const int g = fit_grid(reinterpret_cast<const void*>(&wave_batched_kernel<PREC, NT, 32>), kWaveThreads, dyn);
-      hipLaunchKernelGGL((wave_batched_kernel<PREC, NT, 32>), dim3(g), dim3(kWaveThreads), dyn, stream,
-                         jobs, items, n_items, t_max);
+      const size_t dyn = wave_dynamic_lds(t_max);
+      return with_wave_rows<NT>(tc.th, [&](auto th_c) -> hipError_t {
+        constexpr int TH = decltype(th_c)::value;
+        if (!wave_ok<PREC, NT, TH>(t_max)) return hipErrorInvalidConfiguration;
+        const int g = fit_grid(reinterpret_cast<const void*>(&wave_batched_kernel<PREC, NT, TH>), kWaveThreads, dyn);
+        hipLaunchKernelGGL((wave_batched_kernel<PREC, NT, TH>), dim3(g), dim3(kWaveThreads), dyn, stream,
+                           jobs, items, n_items, t_max);
+        return hipGetLastError();
+      });
     }
-    return hipGetLastError();
   }
   const size_t dyn = dynamic_lds(t_max);
   auto go = [&](auto th_c, auto int_c) -> hipError_t {
@@ -458,8 +485,9 @@ hipError_t launch_fused_nt(const JobDesc& job, int th, hipStream_t stream) {
   const bool integer = (job.flags & BF_FLAG_INTEGER_INPUT) != 0;
   if constexpr (PREC != BF_PLANES_FP32) {
     if (integer) {
-      if (th > 32 && wave_fits<PREC, NT, 64>(job.T)) return launch_wave<PREC, NT, 64>(job, stream);
-      if (wave_fits<PREC, NT, 32>(job.T)) return launch_wave<PREC, NT, 32>(job, stream);
+      const TileChoice tc = choose_tile<PREC, NT>(job, th);
+      if (tc.family == 1)
+        return with_wave_rows<NT>(tc.th, [&](auto th_c) { return launch_wave<PREC, NT, decltype(th_c)::value>(job, stream); });
     }
   } else if (integer) {
     if (th > 32 && staged_fits<PREC, NT, 64>(job.T)) return launch_t<PREC, NT, 64, true>(job, stream);
