@@ -91,6 +91,7 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the error check against the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-tune", action="store_true", help="skip the plan autotuner (bf_plan_tune)")
     ap.add_argument("--eager", action="store_true",
                     help="launch the plan eagerly instead of replaying its HIP graph")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -132,13 +133,21 @@ def main():
 
     stream = torch.cuda.current_stream()
 
+    plans = {}
+
     def timed(prec, out, steps, warmup, use_graph=True):
         """Device time per step of one plan launch (graph replay by default)
-        over all frames; the plan (fits, job table upload) is made once."""
+        over all frames; the plan (fits, job table upload, autotuning) is made
+        once, outside the timed region."""
         plan = native.Plan(make_jobs(out), prec)
         nbytes = plan.workspace_bytes()
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         plan.upload(ws, nbytes, stream)
+        if not args.no_tune:
+            t0 = time.time()
+            plan.tune(stream, reps=2)
+            log("%s: tuned in %.2fs: %s" % (prec, time.time() - t0, plan.describe()["classes"]))
+        plans[prec] = plan.describe()
         for _ in range(warmup):
             plan.launch(stream, use_graph)
         torch.cuda.synchronize()
@@ -205,8 +214,8 @@ def main():
         del a, b
 
     # ---- roofline of the dominant kernel: every frame has the same window and
-    # K, so the plan is one persistent launch per step
-    launches = 1
+    # K, so the plan is one launch per step
+    launches = len(plans[args.precision]["classes"])
     avg_launch_s = ms * 1e-3 / launches
     flops = alg_flops_per_px(K, W) * px / launches   # algorithmic flops of one launch
     achieved = flops / avg_launch_s / 1e12
@@ -216,7 +225,8 @@ def main():
             "traffic": measured_traffic(args.workload, args.precision, n),
             "kernel": ("wave_batched_kernel" if args.precision != "fp32" else "fused_batched_kernel") +
                       " (modulate + row/column MFMA Toeplitz + demodulate + divide)",
-            "alg_flops_per_px": alg_flops_per_px(K, W), "launches_per_step": launches}
+            "alg_flops_per_px": alg_flops_per_px(K, W), "launches_per_step": launches,
+            "plan": plans[args.precision]["classes"]}
 
     # ---- error against the FP64 oracle (sampled rows of frame 0 and the last frame)
     if not args.no_check:

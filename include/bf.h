@@ -211,6 +211,25 @@ int bf_filter_batched(const bf_job* jobs, int n_jobs, bf_planes prec,
  *                 then frees the plan (NULL is ignored).
  */
 typedef struct bf_plan bf_plan;
+/*
+ * bf_plan_tune    autotuner: for every kernel class of an uploaded plan,
+ *                 times `reps` launches of each tile height the class's
+ *                 jobs support (32, 64, and 128 rows for narrow windows) with
+ *                 both grid modes (a persistent grid sized by occupancy, or
+ *                 one workgroup per tile), keeps the fastest, re-uploads the
+ *                 table and remembers the choice for later plans of this
+ *                 process whose classes match (plane format, window class,
+ *                 kernel family, round(log2(pixels))).  Synchronises
+ *                 `hip_stream` (it reads events); writes the jobs' dst
+ *                 buffers.  The output of a plan does not depend on these
+ *                 choices (same per-tile arithmetic).  1 <= reps <= 1000.
+ * bf_plan_describe  writes a JSON description of the plan's classes (window
+ *                 class, family, tile rows and columns, grid mode, items,
+ *                 jobs, tuned) into buf (truncated to len - 1 characters,
+ *                 NUL-terminated); returns the full length, or BF_E_INVALID.
+ */
+int bf_plan_tune(bf_plan* plan, void* hip_stream, int reps);
+int bf_plan_describe(const bf_plan* plan, char* buf, size_t len);
 int bf_plan_create(const bf_job* jobs, int n_jobs, bf_planes prec, bf_plan** plan);
 size_t bf_plan_workspace_bytes(const bf_plan* plan);
 int bf_plan_upload(bf_plan* plan, void* workspace, size_t ws_bytes, void* hip_stream);

@@ -4,8 +4,9 @@
 // A plan resolves every job on the host (arguments, W, the Algorithm 2 fit,
 // the unit-sum spatial profile), picks each job's kernel family and tile
 // geometry, and cuts every image into output tiles ("work items").  Items are
-// grouped into classes that share one kernel instantiation (window class NT,
-// family, tile height); inside a class the jobs are ordered by decreasing
+// grouped into classes that share one kernel (window class NT and family);
+// each class has its own tile height and grid mode, which bf_plan_tune can
+// measure and remember for later plans; inside a class the jobs are ordered by decreasing
 // number of planes 4K+1, so a persistent grid that takes items round-robin
 // gives every workgroup a similar load.  The descriptor table and the items
 // are copied once into the caller's workspace:
@@ -21,6 +22,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <tuple>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -37,12 +40,18 @@ namespace {
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct ClassLaunch {
-  int nt;          // window class: 16-row tiles spanned by 16 rows + 2W halo
-  TileChoice tc;   // kernel family and tile geometry
-  int t_max;       // largest T among the class's jobs (sizes the dynamic LDS)
-  size_t item_off; // first item of the class
-  int n_items;
-  double cost;     // sum over items of (4K+1) x tile area, for ordering
+  int nt = 0;                 // window class: 16-row tiles spanned by 16 rows + 2W halo
+  int family = 0;             // 1 wave kernel, 2 shared-plane staged, 0 general
+  TileChoice tc{};            // current tile geometry (tc.th is tunable)
+  int grid = 0;               // 0: occupancy-sized persistent grid; -1: one workgroup per item; > 0: fixed
+  int t_max = 0;              // largest T among the class's jobs (sizes the dynamic LDS)
+  std::vector<int> jobs;      // ordered by decreasing K
+  std::vector<int> th_options;  // tile heights every job of the class supports
+  size_t item_off = 0;        // first item of the class
+  int n_items = 0;
+  double px = 0.0;            // pixels of the class
+  double cost = 0.0;          // sum over items of (4K+1) x tile area, for ordering
+  bool tuned = false;         // geometry taken from the tuner (or its cache)
 };
 
 struct PlanData {
@@ -52,8 +61,7 @@ struct PlanData {
   std::vector<ClassLaunch> classes;
   int status = BF_OK;      // BF_OK or BF_FIT_NOT_CONVERGED
   size_t items_off = 0;    // byte offset of the items in the workspace
-  size_t ws_bytes = 0;
-  int grid = 0;            // 0: occupancy-sized persistent grid; -1: one item per workgroup
+  size_t ws_bytes = 0;     // sized for the smallest tile height of every class
 };
 
 // Workgroups per class launch.  BF_BATCH_GRID=items gives one workgroup per
@@ -79,16 +87,56 @@ int valid_prec(bf_planes prec) {
   return prec == BF_PLANES_FP32 || prec == BF_PLANES_FP16 || prec == BF_PLANES_BF16;
 }
 
+// ---- tuned geometry, shared by every plan of the process ------------------
+// Key: plane format, window class, kernel family and the class size
+// (round(log2(pixels))); value: tile rows and grid mode measured fastest.
+struct TuneKey {
+  int prec, nt, family, size_log2;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(prec, nt, family, size_log2) < std::tie(o.prec, o.nt, o.family, o.size_log2);
+  }
+};
+struct TuneVal {
+  int th, grid;
+};
+std::mutex g_tune_mutex;
+std::map<TuneKey, TuneVal>* g_tune = new std::map<TuneKey, TuneVal>();  // never freed
+
+TuneKey tune_key(bf_planes prec, const ClassLaunch& c) {
+  return TuneKey{static_cast<int>(prec), c.nt, c.family, static_cast<int>(std::lround(std::log2(std::max(c.px, 1.0))))};
+}
+
+int items_of(const JobDesc& d, int th, int cols) {
+  return ((d.height + th - 1) / th) * ((d.width + cols - 1) / cols);
+}
+
+// Lays the items of every class out in class order (classes already sorted).
+void emit_items(PlanData& p) {
+  p.items.clear();
+  for (ClassLaunch& c : p.classes) {
+    c.item_off = p.items.size();
+    c.cost = 0.0;
+    for (int j : c.jobs) {
+      const JobDesc& d = p.descs[j];
+      for (int y0 = 0; y0 < d.height; y0 += c.tc.th)
+        for (int x0 = 0; x0 < d.width; x0 += c.tc.cols) {
+          p.items.push_back(make_int4(j, x0, y0, 0));
+          c.cost += (4.0 * d.K + 1.0) * c.tc.th * c.tc.cols;
+        }
+    }
+    c.n_items = static_cast<int>(p.items.size() - c.item_off);
+  }
+}
+
 int build_plan(const bf_job* jobs, int n_jobs, bf_planes prec, PlanData& p) {
   if (!jobs || n_jobs < 1) return fail(BF_E_INVALID, "jobs must be non-NULL and n_jobs >= 1");
   if (!valid_prec(prec)) return fail(BF_E_INVALID, "unknown plane precision");
   p = PlanData{};
   p.prec = prec;
-  p.grid = grid_mode_from_env();
+  const int grid_env = grid_mode_from_env();
   const int th_env = tile_rows_from_env();
   p.descs.resize(n_jobs);
-  std::vector<TileChoice> choice(n_jobs);
-  std::map<long, std::vector<int>> by_class;  // key (nt, family, th) -> jobs
+  std::map<long, ClassLaunch> by_class;  // key (nt, family)
   for (int i = 0; i < n_jobs; ++i) {
     Resolved r;
     const int rc = resolve_job(&jobs[i], &r);
@@ -99,38 +147,67 @@ int build_plan(const bf_job* jobs, int n_jobs, bf_planes prec, PlanData& p) {
     if (r.status > p.status) p.status = r.status;
     p.descs[i] = r.desc;
     const int nt = window_tiles(r.desc.W);
-    // fp32 planes with wide windows need too many registers for 64-row tiles
-    const int th_pref = th_env ? th_env : (prec == BF_PLANES_FP32 && nt >= 5) ? 32 : 64;
-    choice[i] = choose_tile(r.desc, prec, th_pref);
-    const long key = (long)nt * 10000 + choice[i].family * 1000 + choice[i].th;
-    by_class[key].push_back(i);
-  }
-  for (auto& kv : by_class) {
-    std::vector<int>& js = kv.second;
-    std::stable_sort(js.begin(), js.end(), [&](int a, int b) { return p.descs[a].K > p.descs[b].K; });
-    ClassLaunch c{};
-    c.nt = static_cast<int>(kv.first / 10000);
-    c.tc = choice[js[0]];
-    c.item_off = p.items.size();
-    for (int j : js) {
-      const JobDesc& d = p.descs[j];
-      c.t_max = std::max(c.t_max, d.T);
-      for (int y0 = 0; y0 < d.height; y0 += c.tc.th)
-        for (int x0 = 0; x0 < d.width; x0 += c.tc.cols) {
-          p.items.push_back(make_int4(j, x0, y0, 0));
-          c.cost += (4.0 * d.K + 1.0) * c.tc.th * c.tc.cols;
-        }
+    // the family is the one the shortest tile gets; taller tiles are options
+    // when every job of the class supports them with the same family
+    const TileChoice base = choose_tile(r.desc, prec, 32);
+    ClassLaunch& c = by_class[(long)nt * 10 + base.family];
+    if (c.jobs.empty()) {
+      c.nt = nt;
+      c.family = base.family;
+      c.tc = base;
+      for (int th : {32, 64, 128}) {
+        const TileChoice t = choose_tile(r.desc, prec, th);
+        if (t.th == th && t.family == base.family) c.th_options.push_back(th);
+      }
+    } else {
+      std::vector<int> keep;
+      for (int th : c.th_options) {
+        const TileChoice t = choose_tile(r.desc, prec, th);
+        if (t.th == th && t.family == base.family) keep.push_back(th);
+      }
+      c.th_options = keep;
     }
-    c.n_items = static_cast<int>(p.items.size() - c.item_off);
-    if (p.items.size() > (size_t)INT32_MAX) return fail(BF_E_UNSUPPORTED, "too many tiles in one batch");
-    p.classes.push_back(c);
+    c.jobs.push_back(i);
+    c.t_max = std::max(c.t_max, r.desc.T);
+    c.px += (double)r.desc.height * r.desc.width;
   }
+  size_t max_items = 0;
+  for (auto& kv : by_class) {
+    ClassLaunch c = kv.second;
+    if (c.th_options.empty()) c.th_options.push_back(32);
+    std::stable_sort(c.jobs.begin(), c.jobs.end(), [&](int a, int b) { return p.descs[a].K > p.descs[b].K; });
+    // default geometry: 64-row tiles (32 for fp32 planes with wide windows),
+    // unless the environment or an earlier tuning run says otherwise
+    int th = th_env ? th_env : (prec == BF_PLANES_FP32 && c.nt >= 5) ? 32 : 64;
+    int grid = grid_env;
+    if (!th_env && !grid_env) {
+      std::lock_guard<std::mutex> lock(g_tune_mutex);
+      auto it = g_tune->find(tune_key(prec, c));
+      if (it != g_tune->end()) {
+        th = it->second.th;
+        grid = it->second.grid;
+        c.tuned = true;
+      }
+    }
+    int pick = c.th_options.front();
+    for (int o : c.th_options)
+      if (o <= th) pick = o;
+    c.tc.th = pick;
+    c.grid = grid;
+    size_t most = 0;
+    for (int j : c.jobs) most += items_of(p.descs[j], c.th_options.front(), c.tc.cols);
+    max_items += most;
+    p.classes.push_back(std::move(c));
+  }
+  if (max_items > (size_t)INT32_MAX) return fail(BF_E_UNSUPPORTED, "too many tiles in one batch");
+  emit_items(p);
   // most expensive class first: when launched one after another its tail is
   // followed by cheaper work
   std::stable_sort(p.classes.begin(), p.classes.end(),
                    [](const ClassLaunch& a, const ClassLaunch& b) { return a.cost > b.cost; });
+  emit_items(p);
   p.items_off = align_up(sizeof(JobDesc) * (size_t)n_jobs, 256);
-  p.ws_bytes = p.items_off + sizeof(int4) * p.items.size();
+  p.ws_bytes = p.items_off + sizeof(int4) * max_items;
   return BF_OK;
 }
 
@@ -211,7 +288,8 @@ int upload_table(const PlanData& p, void* workspace, size_t ws_bytes, hipStream_
   std::memcpy(h, p.descs.data(), sizeof(JobDesc) * p.descs.size());
   std::memset(h + sizeof(JobDesc) * p.descs.size(), 0, p.items_off - sizeof(JobDesc) * p.descs.size());
   std::memcpy(h + p.items_off, p.items.data(), sizeof(int4) * p.items.size());
-  hipError_t e = hipMemcpyAsync(workspace, h, p.ws_bytes, hipMemcpyHostToDevice, stream);
+  const size_t used = p.items_off + sizeof(int4) * p.items.size();
+  hipError_t e = hipMemcpyAsync(workspace, h, used, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return fail(BF_E_DEVICE, std::string("job table copy failed: ") + hipGetErrorString(e));
   if (cs != hipStreamCaptureStatusNone) {
     slot->retired = true;
@@ -231,7 +309,7 @@ int launch_class(const PlanData& p, const ClassLaunch& c, const void* workspace,
   const unsigned char* ws = static_cast<const unsigned char*>(workspace);
   const JobDesc* jobs = reinterpret_cast<const JobDesc*>(ws);
   const int4* items = reinterpret_cast<const int4*>(ws + p.items_off) + c.item_off;
-  const int grid = p.grid < 0 ? c.n_items : p.grid;
+  const int grid = c.grid < 0 ? c.n_items : c.grid;
   hipError_t e = launch_batched(jobs, items, c.n_items, c.t_max, p.prec, c.nt, c.tc, grid, stream);
   if (e != hipSuccess) return fail(BF_E_DEVICE, std::string("batched kernel launch failed: ") + hipGetErrorString(e));
   return BF_OK;
@@ -253,6 +331,7 @@ using namespace bf;
 struct bf_plan {
   PlanData p;
   void* ws = nullptr;   // device workspace of the last upload
+  size_t ws_cap = 0;    // its size
   int device = -1;
   // graph form: classes as independent kernel nodes of one graph
   hipGraphExec_t exec = nullptr;
@@ -377,8 +456,9 @@ extern "C" int bf_plan_upload(bf_plan* plan, void* workspace, size_t ws_bytes, v
   int dev = -1;
   const int rc = upload_table(plan->p, workspace, ws_bytes, stream, &dev);
   if (rc != BF_OK) return rc;
-  if (plan->ws != workspace || plan->device != dev) plan->drop_graph();
+  plan->drop_graph();  // the table may have changed
   plan->ws = workspace;
+  plan->ws_cap = ws_bytes;
   plan->device = dev;
   return BF_OK;
 }
@@ -404,3 +484,97 @@ extern "C" int bf_plan_launch(bf_plan* plan, void* hip_stream, int use_graph) {
 }
 
 extern "C" void bf_plan_destroy(bf_plan* plan) { delete plan; }
+
+extern "C" int bf_plan_tune(bf_plan* plan, void* hip_stream, int reps) {
+  if (!plan) return fail(BF_E_INVALID, "plan is NULL");
+  if (!plan->ws) return fail(BF_E_INVALID, "bf_plan_upload must precede bf_plan_tune");
+  if (reps < 1 || reps > 1000) return fail(BF_E_INVALID, "reps must satisfy 1 <= reps <= 1000");
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  int dev = 0;
+  int rc = stream_device(stream, &dev);
+  if (rc != BF_OK) return rc;
+  if (dev != plan->device) return fail(BF_E_INVALID, "stream belongs to another device than the uploaded table");
+  PlanData& p = plan->p;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  {
+    DeviceGuard g(dev);
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+      if (e0) (void)hipEventDestroy(e0);
+      return fail(BF_E_DEVICE, std::string("event create: ") + hipGetErrorString(e));
+    }
+  }
+  auto time_class = [&](const ClassLaunch& c, float* ms) -> int {
+    int r = upload_table(p, plan->ws, plan->ws_cap, stream, nullptr);
+    if (r == BF_OK) r = launch_class(p, c, plan->ws, stream);  // warm-up
+    if (r != BF_OK) return r;
+    hipError_t e = hipEventRecord(e0, stream);
+    for (int i = 0; e == hipSuccess && i < reps; ++i) {
+      r = launch_class(p, c, plan->ws, stream);
+      if (r != BF_OK) return r;
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    if (e != hipSuccess) return fail(BF_E_DEVICE, std::string("tuning run failed: ") + hipGetErrorString(e));
+    return BF_OK;
+  };
+  for (ClassLaunch& c : p.classes) {
+    float best = 0.f;
+    int best_th = c.tc.th, best_grid = c.grid;
+    bool have = false;
+    for (int th : c.th_options) {
+      for (int grid : {0, -1}) {
+        c.tc.th = th;
+        c.grid = grid;
+        emit_items(p);
+        float ms = 0.f;
+        rc = time_class(c, &ms);
+        if (rc != BF_OK) break;
+        if (!have || ms < best) {
+          best = ms;
+          best_th = th;
+          best_grid = grid;
+          have = true;
+        }
+      }
+      if (rc != BF_OK) break;
+    }
+    c.tc.th = best_th;
+    c.grid = best_grid;
+    if (rc != BF_OK) break;
+    c.tuned = true;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    (*g_tune)[tune_key(p.prec, c)] = TuneVal{best_th, best_grid};
+  }
+  emit_items(p);
+  const int rc2 = upload_table(p, plan->ws, plan->ws_cap, stream, nullptr);
+  plan->drop_graph();
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc != BF_OK ? rc : rc2;
+}
+
+extern "C" int bf_plan_describe(const bf_plan* plan, char* buf, size_t len) {
+  if (!plan) return fail(BF_E_INVALID, "plan is NULL");
+  std::string out = "{\"planes\": " + std::to_string(static_cast<int>(plan->p.prec)) +
+                    ", \"jobs\": " + std::to_string(plan->p.descs.size()) +
+                    ", \"workspace_bytes\": " + std::to_string(plan->p.ws_bytes) + ", \"classes\": [";
+  for (size_t i = 0; i < plan->p.classes.size(); ++i) {
+    const ClassLaunch& c = plan->p.classes[i];
+    out += (i ? ", " : "");
+    out += "{\"nt\": " + std::to_string(c.nt) + ", \"family\": " + std::to_string(c.family) +
+           ", \"tile_rows\": " + std::to_string(c.tc.th) + ", \"tile_cols\": " + std::to_string(c.tc.cols) +
+           ", \"grid\": " + std::to_string(c.grid) + ", \"items\": " + std::to_string(c.n_items) +
+           ", \"jobs\": " + std::to_string(c.jobs.size()) + ", \"t_max\": " + std::to_string(c.t_max) +
+           ", \"tuned\": " + (c.tuned ? "true" : "false") + "}";
+  }
+  out += "]}";
+  if (buf && len > 0) {
+    const size_t n = std::min(len - 1, out.size());
+    std::memcpy(buf, out.data(), n);
+    buf[n] = '\0';
+  }
+  return static_cast<int>(out.size());
+}

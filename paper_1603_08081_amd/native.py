@@ -93,6 +93,10 @@ def _load():
     lib.bf_plan_upload.restype = I
     lib.bf_plan_launch.argtypes = [P, P, I]
     lib.bf_plan_launch.restype = I
+    lib.bf_plan_tune.argtypes = [P, P, I]
+    lib.bf_plan_tune.restype = I
+    lib.bf_plan_describe.argtypes = [P, ctypes.c_char_p, Z]
+    lib.bf_plan_describe.restype = I
     lib.bf_plan_destroy.argtypes = [P]
     lib.bf_plan_destroy.restype = None
     lib.bf_last_error.argtypes = []
@@ -239,6 +243,18 @@ class Plan:
 
     def launch(self, stream=None, use_graph: bool = False) -> int:
         return _check(lib.bf_plan_launch(self.handle, _stream_handle(stream), 1 if use_graph else 0))
+
+    def tune(self, stream=None, reps: int = 3) -> int:
+        """bf_plan_tune: time the tile-height / grid-mode candidates of every
+        class and keep the fastest (synchronises the stream)."""
+        return _check(lib.bf_plan_tune(self.handle, _stream_handle(stream), int(reps)))
+
+    def describe(self) -> dict:
+        import json
+        n = _check(lib.bf_plan_describe(self.handle, None, 0))
+        buf = ctypes.create_string_buffer(n + 1)
+        lib.bf_plan_describe(self.handle, buf, n + 1)
+        return json.loads(buf.value.decode())
 
     def destroy(self):
         if self.handle:

@@ -183,3 +183,23 @@ def test_plan_reports_unconverged_fit_and_rejects_bad_jobs():
     assert native.lib.bf_plan_create(None, 0, 0, ctypes.byref(out)) == native.BF_E_INVALID
     assert out.value is None
     assert native.lib.bf_plan_workspace_bytes(None) == ctypes.c_size_t(-1).value
+
+
+def test_plan_describe_lists_classes():
+    jobs = [_job(), _job(W=30, sigma_s=10.0, height=200, width=300, src_pitch=300, dst_pitch=300,
+                         dst=FAKE_DST + (1 << 24)),
+            _job(integer_input=True)]
+    pl = native.Plan(jobs, "fp16")
+    info = pl.describe()
+    assert info["jobs"] == 3 and info["planes"] == native.PLANES["fp16"]
+    assert info["workspace_bytes"] == pl.workspace_bytes()
+    # W = 9 non-integer, W = 30 non-integer, W = 9 integer: three kernel classes
+    assert len(info["classes"]) == 3
+    assert sum(c["jobs"] for c in info["classes"]) == 3
+    for c in info["classes"]:
+        assert c["tile_rows"] in (32, 64, 128) and c["items"] >= 1 and not c["tuned"]
+    fam = sorted(c["family"] for c in info["classes"])
+    assert fam == [0, 0, 1]   # general path for non-integer images, wave kernel for integer fp16
+    with pytest.raises(native.BfError):
+        pl.tune(stream=0)     # not uploaded yet
+    pl.destroy()

@@ -254,3 +254,45 @@ def test_batch64_mixed_fp16_vs_oracle(batch64):
         worst = max(worst, np.abs(out.ravel()[pix] - ref).max())
     print("batch64 fp16: worst sampled error vs eq. (9) FP64 = %.3e" % worst, flush=True)
     assert worst < 0.5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_tune_keeps_bits_and_is_remembered(prec):
+    torch = _torch()
+    from paper_1603_08081_amd import native
+    specs = _mixed_specs()
+    imgs = _inputs(specs)
+    srcs = [torch.from_numpy(f).cuda() for f in imgs]
+    ref = [torch.full_like(x, -1.0) for x in srcs]
+    out = [torch.full_like(x, -1.0) for x in srcs]
+    out2 = [torch.full_like(x, -1.0) for x in srcs]
+    stream = torch.cuda.current_stream()
+    _batched(native, torch, _jobs(native, specs, srcs, ref), prec, stream)
+    plan = native.Plan(_jobs(native, specs, srcs, out), prec)
+    ws = torch.empty(plan.workspace_bytes(), dtype=torch.uint8, device="cuda")
+    plan.upload(ws, ws.numel(), stream)
+    plan.tune(stream, reps=1)
+    info = plan.describe()
+    print(info, flush=True)
+    assert all(c["tuned"] for c in info["classes"])
+    for o in out:
+        o.fill_(-3.0)
+    plan.launch(stream, use_graph=True)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(ref, out)):
+        assert torch.equal(a, b), "tuned plan, job %d" % i
+    # a later plan with the same classes starts from the tuned geometry
+    plan2 = native.Plan(_jobs(native, specs, srcs, out2), prec)
+    info2 = plan2.describe()
+    assert all(c["tuned"] for c in info2["classes"])
+    geo = {(c["nt"], c["family"]): (c["tile_rows"], c["grid"]) for c in info["classes"]}
+    geo2 = {(c["nt"], c["family"]): (c["tile_rows"], c["grid"]) for c in info2["classes"]}
+    assert geo2 == geo
+    ws2 = torch.empty(plan2.workspace_bytes(), dtype=torch.uint8, device="cuda")
+    plan2.upload(ws2, ws2.numel(), stream)
+    plan2.launch(stream)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(ref, out2)):
+        assert torch.equal(a, b), "cached geometry, job %d" % i
+    plan.destroy()
+    plan2.destroy()
