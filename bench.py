@@ -12,6 +12,7 @@ timed and checked alongside, and so are float32 planes).
 
 Prints ONE JSON line (rank 0).  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp16|bf16|fp32]
+    python bench.py --sweep     # Tables 1-3 analogues, one JSON line per setting
 """
 from __future__ import annotations
 
@@ -76,6 +77,80 @@ def measured_traffic(workload, prec, frames):
     return float(vals["traffic_bytes_per_launch"])
 
 
+# Run-times the paper reports for one 512 x 512 image (Sec. 5, Matlab on a
+# 1.3 GHz laptop CPU; the image had T = 217): Table 1 over sigma_s at
+# sigma_r = 30, Table 2 over sigma_r at sigma_s = 3, Table 3 over eps at
+# sigma_s = 3, sigma_r = 30 (eps = 1e-3 where not varied).
+PAPER_MS = {
+    "table1": {1: 630, 2: 635, 5: 638, 8: 640, 10: 645, 12: 650},
+    "table2": {10: 2100, 15: 1500, 20: 840, 30: 634, 50: 450, 100: 200},
+    "table3": {1e-5: 910, 1e-4: 850, 1e-3: 780, 1e-2: 715, 1e-1: 670},
+}
+
+
+def run_sweep(args):
+    """Tables 1-3 analogues on the GPU: per setting, the fitted K, the latency
+    of one 512 x 512 image, the throughput of a batch of 64 such images, and
+    the error against the FP64 oracles.  One JSON line per setting."""
+    import torch
+
+    import oracle
+    from paper_1603_08081_amd import native
+    from synth import polygon_image
+
+    T = 255
+    n_img = 64
+    imgs = [polygon_image(512, 512, seed=70000 + i) for i in range(n_img)]
+    dev = torch.device("cuda", 0)
+    src = torch.from_numpy(np.stack(imgs)).to(dev)
+    stream = torch.cuda.current_stream()
+    cells = [("table1", dict(sigma_s=float(v), sigma_r=30.0, eps=1e-3)) for v in PAPER_MS["table1"]]
+    cells += [("table2", dict(sigma_s=3.0, sigma_r=float(v), eps=1e-3)) for v in PAPER_MS["table2"]]
+    cells += [("table3", dict(sigma_s=3.0, sigma_r=30.0, eps=float(v))) for v in PAPER_MS["table3"]]
+
+    def events_ms(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for table, c in cells:
+        st, d, e2, em = native.bf_fit_coeffs("gaussian", c["sigma_r"], T, c["eps"], T)
+        K = len(d) - 1
+        W = int(math.ceil(3.0 * c["sigma_s"]))
+        line = {"sweep": table, "sigma_s": c["sigma_s"], "sigma_r": c["sigma_r"], "eps": c["eps"], "T": T,
+                "K": K, "W": W}
+        for prec in ("fp32", "fp16"):
+            out = torch.empty_like(src)
+            jobs = [native.Job(src[i], out[i], spatial="gaussian", sigma_s=c["sigma_s"], W=W, T=T, d=d,
+                               integer_input=True) for i in range(n_img)]
+            line[prec + "_ms_1img"] = round(events_ms(lambda: native.bf_filter(jobs[0], prec, stream=stream),
+                                                      20), 4)
+            plan = native.Plan(jobs, prec)
+            ws = torch.empty(plan.workspace_bytes(), dtype=torch.uint8, device=dev)
+            plan.upload(ws, ws.numel(), stream)
+            plan.tune(stream, reps=2)
+            ms = events_ms(lambda: plan.launch(stream, use_graph=True), 10)
+            line[prec + "_mpix_s_batch64"] = round(n_img * 512 * 512 / (ms * 1e-3) / 1e6, 1)
+            torch.cuda.synchronize()
+            o0 = out[0].cpu().numpy()
+            ref = oracle.fourier(imgs[0], "gaussian", c["sigma_s"], W, d, T)
+            line[prec + "_err_vs_fourier"] = float("%.3g" % np.abs(o0 - ref).max())
+            if prec == "fp32":
+                dire = oracle.direct(imgs[0], "gaussian", c["sigma_s"], W, "gaussian", c["sigma_r"], T=T)
+                line["fp32_err_vs_direct"] = float("%.3g" % np.abs(o0 - dire).max())
+            plan.destroy()
+        key = {"table1": c["sigma_s"], "table2": c["sigma_r"], "table3": c["eps"]}[table]
+        line["paper_ms_1img"] = PAPER_MS[table][int(key) if table != "table3" else key]
+        print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +172,8 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one plain elementwise copy (negation) of this many MiB of "
                          "float32, the known-size reference for HBM byte counters")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the headline line: the Tables 1-3 analogues (one JSON line per setting)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -104,6 +181,10 @@ def main():
               "row stripes with W-row halos; no multi-GPU run is implemented); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.sweep:
+        run_sweep(args)
+        return
 
     import torch
 
