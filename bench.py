@@ -164,6 +164,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32-plane comparison")
     ap.add_argument("--no-bf16", action="store_true", help="skip the bfloat16-plane comparison")
     ap.add_argument("--no-check", action="store_true", help="skip the error check against the oracle")
+    ap.add_argument("--no-fp16-alongside", action="store_true",
+                    help="mixed batches: skip the float16-plane comparison when timing another format")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-tune", action="store_true", help="skip the plan autotuner (bf_plan_tune)")
@@ -190,27 +192,38 @@ def main():
 
     import paper_1603_08081_amd as bfm  # noqa: F401
     from paper_1603_08081_amd import native
-    from synth import WORKLOADS, workload_images
+    from synth import WORKLOADS, batch_specs, workload_images
 
     wl = WORKLOADS[args.workload]
-    if "height" not in wl:
-        raise SystemExit("bench.py times the single-kernel-setting workloads only")
     t0 = time.time()
     imgs = workload_images(args.workload, limit=args.frames)
     n = len(imgs)
-    H, Wd = imgs[0].shape
-    log("generated %d x %dx%d in %.1fs" % (n, H, Wd, time.time() - t0))
+    uniform = "height" in wl
+    log("generated %d images (%.1f Mpx) in %.1fs" % (n, sum(f.size for f in imgs) / 1e6, time.time() - t0))
+    # per-image filter settings; coefficients from the library's own fit
+    if uniform:
+        params = [dict(spatial=wl["spatial"], sigma_s=wl["sigma_s"] or 1.0, W=wl["W"],
+                       range_kind=wl["range_kind"], sigma_r=wl["sigma_r"]) for _ in range(n)]
+    else:
+        params = [dict(spatial=wl["spatial"], sigma_s=sp["sigma_s"], W=sp["W"], range_kind=sp["range_kind"],
+                       sigma_r=sp["sigma_r"]) for sp in batch_specs(wl["n"], wl["seed"])[:n]]
+    fits = {}
+    for p in params:
+        key = (p["range_kind"], p["sigma_r"])
+        if key not in fits:
+            fits[key] = native.bf_fit_coeffs(key[0], key[1], wl["T"], wl["eps"], wl["K_max"])[1]
+        p["d"] = fits[key]
+        p["K"] = len(p["d"]) - 1
     dev = torch.device("cuda", 0)
-    src = torch.from_numpy(np.stack(imgs)).to(dev)
-    dst = torch.empty_like(src)
-    st, d, e2, em = native.bf_fit_coeffs(wl["range_kind"], wl["sigma_r"], wl["T"], wl["eps"], wl["K_max"])
-    K = len(d) - 1
-    W = wl["W"]
+    srcs = [torch.from_numpy(f).to(dev) for f in imgs]
+    dst = [torch.empty_like(x) for x in srcs]
+    px = sum(f.size for f in imgs)
+    alg_flops = sum(alg_flops_per_px(p["K"], p["W"]) * f.size for p, f in zip(params, imgs))
 
-    def make_jobs(prec_dst):
-        return [native.Job(src[i], prec_dst[i], spatial=wl["spatial"], sigma_s=wl["sigma_s"] or 1.0, W=W,
-                           range_kind=wl["range_kind"], sigma_r=wl["sigma_r"], T=wl["T"], d=d,
-                           integer_input=True) for i in range(n)]
+    def make_jobs(outs):
+        return [native.Job(srcs[i], outs[i], spatial=p["spatial"], sigma_s=p["sigma_s"], W=p["W"],
+                           range_kind=p["range_kind"], sigma_r=p["sigma_r"], T=wl["T"], d=p["d"],
+                           integer_input=True) for i, p in enumerate(params)]
 
     stream = torch.cuda.current_stream()
 
@@ -218,7 +231,7 @@ def main():
 
     def timed(prec, out, steps, warmup, use_graph=True):
         """Device time per step of one plan launch (graph replay by default)
-        over all frames; the plan (fits, job table upload, autotuning) is made
+        over all images; the plan (fits, job table upload, autotuning) is made
         once, outside the timed region."""
         plan = native.Plan(make_jobs(out), prec)
         nbytes = plan.workspace_bytes()
@@ -259,7 +272,6 @@ def main():
         return e0.elapsed_time(e1) / steps
 
     ms = timed(args.precision, dst, args.steps, args.warmup, use_graph=not args.eager)
-    px = n * H * Wd
     value = px / (ms * 1e-3) / 1e6
     log("%s planes: %.3f ms/step, %.1f Mpix/s (plan, graph replay)" % (args.precision, ms, value))
 
@@ -267,24 +279,28 @@ def main():
     ms_call = timed_call(args.precision, dst, max(2, args.steps // 2))
     log("%s planes: %.3f ms/step through bf_filter_batched" % (args.precision, ms_call))
     extra["batched_call_ms_per_step"] = round(ms_call, 3)
-    dstb = None
+    outs = {args.precision: dst}
     if not args.no_bf16 and args.precision != "bf16":
-        dstb = torch.empty_like(src)
-        msb = timed("bf16", dstb, args.steps, 1)
+        outs["bf16"] = [torch.empty_like(x) for x in srcs]
+        msb = timed("bf16", outs["bf16"], args.steps, 1)
         vb = px / (msb * 1e-3) / 1e6
         log("bf16 planes: %.3f ms/step, %.1f Mpix/s" % (msb, vb))
         extra["bf16_value"] = round(vb, 1)
         extra["bf16_ms_per_step"] = round(msb, 3)
     if not args.no_fp32 and args.precision != "fp32":
-        dst32 = torch.empty_like(src)
-        ms32 = timed("fp32", dst32, max(2, args.steps // 4), 1)
+        outs["fp32"] = [torch.empty_like(x) for x in srcs]
+        ms32 = timed("fp32", outs["fp32"], max(2, args.steps // 4), 1)
         v32 = px / (ms32 * 1e-3) / 1e6
         log("fp32 planes: %.3f ms/step, %.1f Mpix/s" % (ms32, v32))
         extra["fp32_value"] = round(v32, 1)
         extra["fp32_ms_per_step"] = round(ms32, 3)
         extra["speedup_vs_fp32"] = round(value / v32, 3)
-    else:
-        dst32 = dst if args.precision == "fp32" else None
+    if args.precision != "fp16" and not args.no_fp16_alongside and not uniform:
+        outs["fp16"] = [torch.empty_like(x) for x in srcs]
+        ms16 = timed("fp16", outs["fp16"], args.steps, 1)
+        extra["fp16_value"] = round(px / (ms16 * 1e-3) / 1e6, 1)
+        extra["fp16_ms_per_step"] = round(ms16, 3)
+        log("fp16 planes: %.3f ms/step, %.1f Mpix/s" % (ms16, extra["fp16_value"]))
 
     if args.calib_copy_mib > 0:
         a = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device=dev)
@@ -294,80 +310,101 @@ def main():
         log("calibration copy: %d MiB read + %d MiB written" % (args.calib_copy_mib, args.calib_copy_mib))
         del a, b
 
-    # ---- roofline of the dominant kernel: every frame has the same window and
-    # K, so the plan is one launch per step
+    # ---- roofline of the dominant kernel: with one kernel class (every image
+    # with the same window class and kernel family) the plan is one launch per
+    # step; with several, the launches share the step and the figure is their
+    # average
     launches = len(plans[args.precision]["classes"])
     avg_launch_s = ms * 1e-3 / launches
-    flops = alg_flops_per_px(K, W) * px / launches   # algorithmic flops of one launch
+    flops = alg_flops / launches   # algorithmic flops of one launch
     achieved = flops / avg_launch_s / 1e12
     peak = PEAK_TFLOPS[args.precision]
+    fam = {1: "wave_batched_kernel", 2: "fused_batched_kernel", 0: "fused_batched_kernel (general phase)"}
+    main_family = max(plans[args.precision]["classes"], key=lambda c: c["items"])["family"]
     roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
-            "traffic": measured_traffic(args.workload, args.precision, n),
-            "kernel": ("wave_batched_kernel" if args.precision != "fp32" else "fused_batched_kernel") +
-                      " (modulate + row/column MFMA Toeplitz + demodulate + divide)",
-            "alg_flops_per_px": alg_flops_per_px(K, W), "launches_per_step": launches,
+            "traffic": measured_traffic(args.workload, args.precision, n) if launches == 1 else None,
+            "kernel": fam[main_family] + " (modulate + row/column MFMA Toeplitz + demodulate + divide)",
+            "alg_flops_per_px": round(alg_flops / px, 1), "launches_per_step": launches,
             "plan": plans[args.precision]["classes"]}
+    if roof["traffic"] is not None:
+        roof["hbm_gbs"] = round(roof["traffic"] / avg_launch_s / 1e9, 1)
+        roof["hbm_frac"] = round(roof["hbm_gbs"] / PEAK_HBM_GBS, 4)
 
-    # ---- error against the FP64 oracle (sampled rows of frame 0 and the last frame)
+    # ---- error against the FP64 oracle: every pixel of sampled rows (borders,
+    # window edges, middle, seeded random) of the first and last image (and
+    # two more for mixed batches)
     if not args.no_check:
         import oracle
-        out16 = dst.cpu().numpy()
-        out32 = dst32.cpu().numpy() if dst32 is not None else None
-        rows = np.unique(np.array([0, 1, W - 1, W, H // 2, H - W - 1, H - 2, H - 1] +
-                                  list(np.random.default_rng(1).integers(0, H, 4))))
-        pix = (rows[:, None] * Wd + np.arange(Wd)[None, :]).ravel()
-        outb = dstb.cpu().numpy() if dstb is not None else None
-        errs16, errs32, errsd, errsb = [], [], [], []
-        for fi in sorted({0, n - 1}):
-            ref = oracle.fourier(imgs[fi], wl["spatial"], wl["sigma_s"] or 1.0, W, d, wl["T"], pixels=pix)
-            dire = oracle.direct(imgs[fi], wl["spatial"], wl["sigma_s"] or 1.0, W, wl["range_kind"],
-                                 wl["sigma_r"], T=wl["T"], pixels=pix)
-            errs16.append(np.abs(out16[fi].ravel()[pix] - ref).max())
-            errsd.append(np.abs(out16[fi].ravel()[pix] - dire).max())
-            if out32 is not None:
-                errs32.append(np.abs(out32[fi].ravel()[pix] - ref).max())
-            if outb is not None:
-                errsb.append(np.abs(outb[fi].ravel()[pix] - ref).max())
-        extra["max_err_vs_fourier_fp64"] = float("%.4g" % max(errs16))
+        check = sorted({0, n - 1} if uniform else {0, n // 3, (2 * n) // 3, n - 1})
+        errs = {k: [] for k in outs}
+        errsd = []
+        nrows = 0
+        for fi in check:
+            p = params[fi]
+            H, Wd = imgs[fi].shape
+            W = p["W"]
+            rows = np.unique(np.array([0, 1, W - 1, W, H // 2, H - W - 1, H - 2, H - 1] +
+                                      list(np.random.default_rng(fi).integers(0, H, 4))))
+            nrows += len(rows)
+            pix = (rows[:, None] * Wd + np.arange(Wd)[None, :]).ravel()
+            ref = oracle.fourier(imgs[fi], p["spatial"], p["sigma_s"], W, p["d"], wl["T"], pixels=pix)
+            dire = oracle.direct(imgs[fi], p["spatial"], p["sigma_s"], W, p["range_kind"], p["sigma_r"],
+                                 T=wl["T"], pixels=pix)
+            for k, o in outs.items():
+                got = o[fi].cpu().numpy().ravel()[pix]
+                errs[k].append(float(np.abs(got - ref).max()))
+                if k == args.precision:
+                    errsd.append(float(np.abs(got - dire).max()))
+        extra["max_err_vs_fourier_fp64"] = float("%.4g" % max(errs[args.precision]))
         extra["max_err_vs_direct_fp64"] = float("%.4g" % max(errsd))
-        if errs32:
-            extra["fp32_max_err_vs_fourier_fp64"] = float("%.4g" % max(errs32))
-        if errsb:
-            extra["bf16_max_err_vs_fourier_fp64"] = float("%.4g" % max(errsb))
-            extra["bf16_meets_0p5"] = bool(max(errsb) < 0.5)
-        extra["err_sample"] = "all pixels of %d rows of frames %s" % (len(rows), sorted({0, n - 1}))
-        extra["meets_0p5"] = bool(max(errs16) < 0.5)
+        for k in outs:
+            if k != args.precision:
+                extra["%s_max_err_vs_fourier_fp64" % k] = float("%.4g" % max(errs[k]))
+        if "bf16" in errs:
+            extra["bf16_meets_0p5"] = bool(max(errs["bf16"]) < 0.5)
+        extra["err_sample"] = "all pixels of %d rows of images %s" % (nrows, check)
+        extra["meets_0p5"] = bool(max(errs[args.precision]) < 0.5)
 
-    # ---- CPU baseline: the FP64 oracle of eq. (9) on a bounded sample of frame 0
+    # ---- CPU baseline: the FP64 oracle of eq. (9) on a bounded sample of image 0
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        f0 = imgs[0]
-        oracle.fourier(f0, wl["spatial"], wl["sigma_s"] or 1.0, W, d, wl["T"],
-                       pixels=np.arange(Wd))  # warm (threads, page-in)
+        f0, p0 = imgs[0], params[0]
+        H0, W0 = f0.shape
+        ora = lambda pix: oracle.fourier(f0, p0["spatial"], p0["sigma_s"], p0["W"], p0["d"], wl["T"], pixels=pix)
+        ora(np.arange(W0))  # warm (threads, page-in)
         t1 = time.time()
-        oracle.fourier(f0, wl["spatial"], wl["sigma_s"] or 1.0, W, d, wl["T"], pixels=np.arange(2 * Wd))
+        ora(np.arange(2 * W0))
         per_row = (time.time() - t1) / 2
-        nrows = int(max(1, min(H, args.cpu_seconds / max(per_row, 1e-6))))
-        r0 = (H - nrows) // 2
-        pix = np.arange(r0 * Wd, (r0 + nrows) * Wd)
+        nr = int(max(1, min(H0, args.cpu_seconds / max(per_row, 1e-6))))
+        r0 = (H0 - nr) // 2
+        pix = np.arange(r0 * W0, (r0 + nr) * W0)
         t1 = time.time()
-        oracle.fourier(f0, wl["spatial"], wl["sigma_s"] or 1.0, W, d, wl["T"], pixels=pix)
+        ora(pix)
         dt = time.time() - t1
         cpu = {"value": round(pix.size / dt / 1e6, 4), "unit": "Mpix/s", "cores": oracle.num_threads(),
                "kind": "oracle",
-               "sample": "eq. (9) in FP64 on %d full rows (%d px) of frame 0, %.1f s" % (nrows, pix.size, dt)}
+               "sample": "eq. (9) in FP64 on %d full rows (%d px) of image 0, %.1f s" % (nr, pix.size, dt)}
 
+    if uniform:
+        H, Wd = imgs[0].shape
+        config = {"workload": args.workload, "frames": n, "height": H, "width": Wd,
+                  "spatial": wl["spatial"], "sigma_s": wl["sigma_s"], "W": wl["W"],
+                  "range": wl["range_kind"], "sigma_r": wl["sigma_r"], "T": wl["T"], "K": params[0]["K"],
+                  "planes": args.precision, "accumulation": "fp32"}
+    else:
+        config = {"workload": args.workload, "images": n, "megapixels": round(px / 1e6, 2),
+                  "sides": "round(exp U[ln 256, ln 4096]) each", "spatial": wl["spatial"],
+                  "W": [min(p["W"] for p in params), max(p["W"] for p in params)],
+                  "range": "gaussian or exponential per image",
+                  "K": [min(p["K"] for p in params), max(p["K"] for p in params)], "T": wl["T"],
+                  "eps": wl["eps"], "K_max": wl["K_max"], "planes": args.precision, "accumulation": "fp32"}
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpix/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.precision, "data": "synthetic",
-        "config": {"workload": args.workload, "frames": n, "height": H, "width": Wd,
-                   "spatial": wl["spatial"], "sigma_s": wl["sigma_s"], "W": W,
-                   "range": wl["range_kind"], "sigma_r": wl["sigma_r"], "T": wl["T"], "K": K,
-                   "planes": args.precision, "accumulation": "fp32"},
+        "dtype": args.precision, "data": "synthetic", "config": config,
         "roofline": roof, "cpu_baseline": cpu,
     }
     line.update(extra)
