@@ -9,8 +9,8 @@ from __future__ import annotations
 
 
 def filter(img, *, spatial="gaussian", sigma_s=3.0, W=-1, range_kind="gaussian", sigma_r=30.0,
-           T=255, eps=1e-2, K_max=None, d=None, precision="fp32", integer_input=False, out=None,
-           stream=None):
+           T=255, eps=1e-2, K_max=None, d=None, phi_table=None, precision="fp32", integer_input=False,
+           out=None, stream=None):
     """Filter one 2-D float32 CUDA tensor with eq. (9); returns (out, status)."""
     import torch
 
@@ -22,6 +22,7 @@ def filter(img, *, spatial="gaussian", sigma_s=3.0, W=-1, range_kind="gaussian",
     if out is None:
         out = torch.empty_like(img, memory_format=torch.contiguous_format)
     job = native.Job(img, out, spatial=spatial, sigma_s=sigma_s, W=W, range_kind=range_kind,
-                     sigma_r=sigma_r, T=T, eps=eps, K_max=K_max, d=d, integer_input=integer_input)
+                     sigma_r=sigma_r, T=T, eps=eps, K_max=K_max, d=d, phi_table=phi_table,
+                     integer_input=integer_input)
     st = native.bf_filter(job, precision, stream=stream)
     return out, st

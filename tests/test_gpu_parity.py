@@ -192,3 +192,35 @@ def test_constant_image_unchanged():
     for prec in ("fp32", "fp16", "bf16"):
         out, _ = gpu_filter(f, prec, spatial="gaussian", sigma_s=4.0, W=12, T=255, d=r.d, integer_input=True)
         assert np.abs(out - 131.0).max() <= (TOL_FP32 if prec == "fp32" else 0.05), prec
+
+
+def _table_kernels(T):
+    t = np.arange(T + 1, dtype=np.float64)
+    tukey = np.where(t < 40.0, (1.0 - (t / 40.0) ** 2) ** 2, 0.0)      # Tukey biweight, support 40
+    cauchy = 1.0 / (1.0 + (t / 12.0) ** 2)                            # Cauchy / Lorentzian
+    box = (t <= 20).astype(np.float64)                                 # hard range window
+    return {"tukey": tukey, "cauchy": cauchy, "box": box}
+
+
+@pytest.mark.parametrize("name", ["tukey", "cauchy", "box"])
+def test_sampled_range_kernels(name):
+    """Range kernels given only by their samples phi(0..T) (BF_RANGE_TABLE):
+    the library fits them itself (Algorithm 2); GPU FP32 must match eq. (9)
+    in FP64 with the oracle's own fit, and FP16 planes stay < 0.5."""
+    T = 255
+    phi = _table_kernels(T)[name]
+    f = polygon_image(150, 170, seed=31)
+    r = oracle.fit_kernel("table", 0.0, T, 1e-3, 120, table=phi)
+    for prec, tol in (("fp32", TOL_FP32), ("fp16", 0.5)):
+        out, st = gpu_filter(f, prec, spatial="gaussian", sigma_s=4.0, W=12, T=T, range_kind="table",
+                             phi_table=phi, eps=1e-3, K_max=120, integer_input=True)
+        ref = oracle.fourier(f, "gaussian", 4.0, 12, r.d, T)
+        err = np.abs(out - ref).max()
+        _report("table kernel %s %s (K=%d)" % (name, prec, r.K), err)
+        assert err <= tol
+    # and against eq. (1) with the sampled kernel itself, within the eq. (12)
+    # bound where that bound means something (eps below w(0))
+    w0 = oracle.center_weight("gaussian", 4.0, 12)
+    if r.E < w0:
+        dire = oracle.direct(f, "gaussian", 4.0, 12, "table", T=T, table=phi)
+        assert np.abs(out - dire).max() <= oracle.accuracy_bound(T, r.E, w0) + 0.5
