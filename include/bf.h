@@ -117,6 +117,11 @@ int bf_fit_coeffs(bf_range_kind kind, double sigma_r, const double* phi_table, i
  *                   the fit is skipped and range/sigma_r/phi_table/eps/K_max are
  *                   not used (T still sets w = pi / T)
  *   flags           BF_FLAG_* bits
+ *   f_max           largest pixel value, 0 <= f_max <= BF_MAX_T; 0 means T.  Pixels
+ *                   lie in [0, f_max] while T only has to bound the differences
+ *                   |f(i - j) - f(i)| inside each window (the local dynamic range of
+ *                   Sec. 3, see bf_dynamic_range), so T may be smaller than f_max.
+ *                   With BF_FLAG_INTEGER_INPUT the gray-level tables cover 0..f_max.
  */
 typedef struct bf_job {
   const float* src;
@@ -135,6 +140,7 @@ typedef struct bf_job {
   const double* d;
   int K;
   int flags;
+  int f_max;
 } bf_job;
 
 /*
@@ -235,6 +241,29 @@ size_t bf_plan_workspace_bytes(const bf_plan* plan);
 int bf_plan_upload(bf_plan* plan, void* workspace, size_t ws_bytes, void* hip_stream);
 int bf_plan_launch(bf_plan* plan, void* hip_stream, int use_graph);
 void bf_plan_destroy(bf_plan* plan);
+
+/*
+ * bf_dynamic_range -- the dynamic range T of Sec. 3 measured on the image:
+ * the largest |f(i - j) - f(i)| over all pixels i and offsets j in
+ * [-W, W]^2, i.e. the smallest T with which eq. (1) evaluates the range
+ * kernel only on [-T, T]; rounded up to an integer (0 for a constant image).
+ * The borders need no folding: under the half-sample symmetric extension a
+ * folded neighbour is a pixel no farther away than its offset, so it adds no
+ * new pair.  A smaller T needs fewer harmonics for the same tolerance
+ * (Algorithm 2 with w = pi / T); pass it as bf_job.T with f_max set to the
+ * largest pixel value.
+ *   src, height, width, src_pitch   device float32 image, pitch in elements
+ *   W           window half-width, 0 <= W <= BF_MAX_W
+ *   T_out       device int that receives the result
+ *   workspace   device memory of bf_dynamic_range_workspace_bytes(height,
+ *               width) bytes (4 B per pixel plus one float per 64x64 tile),
+ *               16-byte aligned
+ *   hip_stream  stream to enqueue on (three launches; asynchronous)
+ * Returns BF_OK, BF_E_INVALID, BF_E_WORKSPACE or BF_E_DEVICE.
+ */
+size_t bf_dynamic_range_workspace_bytes(int height, int width);
+int bf_dynamic_range(const float* src, int height, int width, int src_pitch, int W, int* T_out,
+                     void* workspace, size_t ws_bytes, void* hip_stream);
 
 /* Thread-local text describing the last non-OK status of this thread. */
 const char* bf_last_error(void);

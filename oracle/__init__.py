@@ -12,6 +12,7 @@ Parts:
   filters.fourier           eq. (9), FP64, C + OpenMP (the GPU's parity target)
   filters.shiftable_alg1    Algorithm 1 in complex FP64 (numpy)
   filters.brute_direct      eq. (1) in pure Python, tiny images
+  dynamic_range.local_dynamic_range   the dynamic range T of Sec. 3 measured on an image
 """
 from .fit import (  # noqa: F401
     FitResult, accuracy_bound, back_substitute, fit_kernel, progressive_fit, sample_kernel, series,
@@ -20,3 +21,4 @@ from .filters import (  # noqa: F401
     brute_direct, build, center_weight, direct, fourier, num_threads, shiftable_alg1,
     spatial_profile,
 )
+from .dynamic_range import brute_local_dynamic_range, local_dynamic_range  # noqa: F401,E402

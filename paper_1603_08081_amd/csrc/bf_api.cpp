@@ -66,6 +66,7 @@ int resolve_job(const bf_job* j, Resolved* out) {
   if (W >= j->height || W >= j->width)
     return fail(BF_E_INVALID, "W must be smaller than both image sides (symmetric border)");
   if (j->T < 1 || j->T > BF_MAX_T) return fail(BF_E_INVALID, "T must satisfy 1 <= T <= BF_MAX_T");
+  if (j->f_max < 0 || j->f_max > BF_MAX_T) return fail(BF_E_INVALID, "f_max must satisfy 0 <= f_max <= BF_MAX_T");
   // src and dst ranges must not overlap
   const uintptr_t s0 = reinterpret_cast<uintptr_t>(j->src);
   const uintptr_t s1 = s0 + sizeof(float) * ((size_t)(j->height - 1) * j->src_pitch + j->width);
@@ -102,8 +103,10 @@ int resolve_job(const bf_job* j, Resolved* out) {
   jd.W = W;
   jd.K = static_cast<int>(d.size()) - 1;
   jd.T = j->T;
+  jd.F = j->f_max > 0 ? j->f_max : j->T;
   jd.flags = j->flags;
-  jd.c0 = 0.5f * static_cast<float>(j->T);
+  // centre of the gray-level range: |f - c0| <= F / 2 before 16-bit rounding
+  jd.c0 = 0.5f * static_cast<float>(jd.F);
   // unit-sum 1-D profile (eq. (2) is separable: w(x, y) = w1(x) w1(y))
   double sum = 0.0;
   std::vector<double> w1(2 * W + 1);

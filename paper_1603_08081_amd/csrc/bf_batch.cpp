@@ -45,6 +45,7 @@ struct ClassLaunch {
   TileChoice tc{};            // current tile geometry (tc.th is tunable)
   int grid = 0;               // 0: occupancy-sized persistent grid; -1: one workgroup per item; > 0: fixed
   int t_max = 0;              // largest T among the class's jobs (sizes the dynamic LDS)
+  int f_max = 0;              // largest gray-level table extent F among them
   std::vector<int> jobs;      // ordered by decreasing K
   std::vector<int> th_options;  // tile heights every job of the class supports
   size_t item_off = 0;        // first item of the class
@@ -169,6 +170,7 @@ int build_plan(const bf_job* jobs, int n_jobs, bf_planes prec, PlanData& p) {
     }
     c.jobs.push_back(i);
     c.t_max = std::max(c.t_max, r.desc.T);
+    c.f_max = std::max(c.f_max, r.desc.F);
     c.px += (double)r.desc.height * r.desc.width;
   }
   size_t max_items = 0;
@@ -310,7 +312,7 @@ int launch_class(const PlanData& p, const ClassLaunch& c, const void* workspace,
   const JobDesc* jobs = reinterpret_cast<const JobDesc*>(ws);
   const int4* items = reinterpret_cast<const int4*>(ws + p.items_off) + c.item_off;
   const int grid = c.grid < 0 ? c.n_items : c.grid;
-  hipError_t e = launch_batched(jobs, items, c.n_items, c.t_max, p.prec, c.nt, c.tc, grid, stream);
+  hipError_t e = launch_batched(jobs, items, c.n_items, c.t_max, c.f_max, p.prec, c.nt, c.tc, grid, stream);
   if (e != hipSuccess) return fail(BF_E_DEVICE, std::string("batched kernel launch failed: ") + hipGetErrorString(e));
   return BF_OK;
 }
@@ -568,6 +570,7 @@ extern "C" int bf_plan_describe(const bf_plan* plan, char* buf, size_t len) {
            ", \"tile_rows\": " + std::to_string(c.tc.th) + ", \"tile_cols\": " + std::to_string(c.tc.cols) +
            ", \"grid\": " + std::to_string(c.grid) + ", \"items\": " + std::to_string(c.n_items) +
            ", \"jobs\": " + std::to_string(c.jobs.size()) + ", \"t_max\": " + std::to_string(c.t_max) +
+           ", \"f_max\": " + std::to_string(c.f_max) +
            ", \"tuned\": " + (c.tuned ? "true" : "false") + "}";
   }
   out += "]}";

@@ -44,17 +44,17 @@ TileChoice choose_prec(const JobDesc& job, int th_pref) {
   }
 }
 template <int PREC>
-hipError_t batched_prec(const JobDesc* jobs, const int4* items, int n, int t_max, int nt, TileChoice tc, int grid,
+hipError_t batched_prec(const JobDesc* jobs, const int4* items, int n, int t_max, int f_max, int nt, TileChoice tc, int grid,
                         hipStream_t st) {
   switch (nt) {
-    case 2: return fused_detail::launch_batched_class<PREC, 2>(jobs, items, n, t_max, tc, grid, st);
-    case 3: return fused_detail::launch_batched_class<PREC, 3>(jobs, items, n, t_max, tc, grid, st);
-    case 4: return fused_detail::launch_batched_class<PREC, 4>(jobs, items, n, t_max, tc, grid, st);
-    case 5: return fused_detail::launch_batched_class<PREC, 5>(jobs, items, n, t_max, tc, grid, st);
-    case 6: return fused_detail::launch_batched_class<PREC, 6>(jobs, items, n, t_max, tc, grid, st);
-    case 7: return fused_detail::launch_batched_class<PREC, 7>(jobs, items, n, t_max, tc, grid, st);
-    case 8: return fused_detail::launch_batched_class<PREC, 8>(jobs, items, n, t_max, tc, grid, st);
-    case 9: return fused_detail::launch_batched_class<PREC, 9>(jobs, items, n, t_max, tc, grid, st);
+    case 2: return fused_detail::launch_batched_class<PREC, 2>(jobs, items, n, t_max, f_max, tc, grid, st);
+    case 3: return fused_detail::launch_batched_class<PREC, 3>(jobs, items, n, t_max, f_max, tc, grid, st);
+    case 4: return fused_detail::launch_batched_class<PREC, 4>(jobs, items, n, t_max, f_max, tc, grid, st);
+    case 5: return fused_detail::launch_batched_class<PREC, 5>(jobs, items, n, t_max, f_max, tc, grid, st);
+    case 6: return fused_detail::launch_batched_class<PREC, 6>(jobs, items, n, t_max, f_max, tc, grid, st);
+    case 7: return fused_detail::launch_batched_class<PREC, 7>(jobs, items, n, t_max, f_max, tc, grid, st);
+    case 8: return fused_detail::launch_batched_class<PREC, 8>(jobs, items, n, t_max, f_max, tc, grid, st);
+    case 9: return fused_detail::launch_batched_class<PREC, 9>(jobs, items, n, t_max, f_max, tc, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -68,12 +68,12 @@ TileChoice choose_tile(const JobDesc& job, bf_planes prec, int th_pref) {
   }
 }
 
-hipError_t launch_batched(const JobDesc* jobs_dev, const int4* items_dev, int n_items, int t_max, bf_planes prec,
-                          int nt, TileChoice tc, int grid, hipStream_t stream) {
+hipError_t launch_batched(const JobDesc* jobs_dev, const int4* items_dev, int n_items, int t_max, int f_max,
+                          bf_planes prec, int nt, TileChoice tc, int grid, hipStream_t stream) {
   switch (prec) {
-    case BF_PLANES_FP32: return batched_prec<BF_PLANES_FP32>(jobs_dev, items_dev, n_items, t_max, nt, tc, grid, stream);
-    case BF_PLANES_FP16: return batched_prec<BF_PLANES_FP16>(jobs_dev, items_dev, n_items, t_max, nt, tc, grid, stream);
-    case BF_PLANES_BF16: return batched_prec<BF_PLANES_BF16>(jobs_dev, items_dev, n_items, t_max, nt, tc, grid, stream);
+    case BF_PLANES_FP32: return batched_prec<BF_PLANES_FP32>(jobs_dev, items_dev, n_items, t_max, f_max, nt, tc, grid, stream);
+    case BF_PLANES_FP16: return batched_prec<BF_PLANES_FP16>(jobs_dev, items_dev, n_items, t_max, f_max, nt, tc, grid, stream);
+    case BF_PLANES_BF16: return batched_prec<BF_PLANES_BF16>(jobs_dev, items_dev, n_items, t_max, f_max, nt, tc, grid, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -14,7 +14,7 @@ namespace fused_detail {
 template <int PREC, int NT>
 TileChoice choose_tile(const JobDesc& job, int th_pref);
 template <int PREC, int NT>
-hipError_t launch_batched_class(const JobDesc* jobs, const int4* items, int n_items, int t_max,
+hipError_t launch_batched_class(const JobDesc* jobs, const int4* items, int n_items, int t_max, int f_max,
                                 TileChoice tc, int grid, hipStream_t stream);
 }  // namespace fused_detail
 

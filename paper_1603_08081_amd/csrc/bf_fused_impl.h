@@ -121,7 +121,7 @@ struct Lds {
   static constexpr bool fits = total + kTabBytes * 256 + 8 * 510 <= kLdsLimit;
 };
 
-inline size_t dynamic_lds(int T) { return (size_t)kTabBytes * (T + 1) + sizeof(float2) * 2 * (size_t)T; }
+inline size_t dynamic_lds(int T, int F) { return (size_t)kTabBytes * (F + 1) + sizeof(float2) * 2 * (size_t)T; }
 
 template <int I, int N, typename F>
 __device__ __forceinline__ void static_for(F&& f) {
@@ -215,7 +215,7 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
     for (int idx = tid; idx < FROWS * LWU; idx += NTHR) {
       const int r = idx / LWU, c = idx - r * LWU;
       float v = src[(size_t)fold(Y0 - W + r, H) * sp + fold(X0 - Wal + c, Wd)];
-      v = fminf(fmaxf(v, 0.f), (float)T);  // NaN -> 0; the flag promises integers in [0, T]
+      v = fminf(fmaxf(v, 0.f), (float)job.F);  // NaN -> 0; the flag promises integers in [0, F]
       ftile[r][c] = (uint16_t)((int)v * kTabBytes);
     }
   }
@@ -279,7 +279,7 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
       // per-harmonic table, entry f: fp32 (c, s, (f-c0) c, (f-c0) s) for fp32
       // planes; for 16-bit planes (d_k c, d_k s) in fp32 for the demodulation
       // and (c, s, (f-c0) c, (f-c0) s) rounded to the plane format
-      for (int f = tid; f <= T; f += NTHR) {
+      for (int f = tid; f <= job.F; f += NTHR) {
         const float m = reduce_2t((float)k * (float)f, pt);
         const float2 cs = lut[min(max((int)m, 0), 2 * T - 1)];
         const float v = (float)f - c0;
@@ -495,7 +495,7 @@ __global__ void __launch_bounds__(kThreadsFor<PREC>) fused_kernel(const JobDesc 
   // dynamic: per-harmonic table [(T+1) x 16 B], then cos/sin(pi m / T) [2T x 8 B]
   extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
   fused_tile<PREC, NT, TH, INTEGER>(job, blockIdx.x * Geo<PREC, NT>::COLS, blockIdx.y * TH, smem, dyn,
-                                    reinterpret_cast<float2*>(dyn + (size_t)kTabBytes * (job.T + 1)), true);
+                                    reinterpret_cast<float2*>(dyn + (size_t)kTabBytes * (job.F + 1)), true);
 }
 
 // Persistent form: workgroup b processes items b, b + gridDim.x, ... of a
@@ -524,7 +524,7 @@ hipError_t launch_t(const JobDesc& job, hipStream_t stream) {
   using G = Geo<PREC, NT>;
   static_assert(G::THREADS == kThreadsFor<PREC>, "launch bounds");
   dim3 grid((job.width + G::COLS - 1) / G::COLS, (job.height + TH - 1) / TH);
-  const size_t dyn = dynamic_lds(job.T);
+  const size_t dyn = dynamic_lds(job.T, job.F);
   constexpr bool staged = INTEGER && Lds<PREC, NT, TH, true>::fits;
   if (Lds<PREC, NT, TH, staged>::total + dyn > kLdsLimit) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((fused_kernel<PREC, NT, TH, INTEGER>), grid, dim3(G::THREADS), dyn, stream, job);
@@ -533,8 +533,8 @@ hipError_t launch_t(const JobDesc& job, hipStream_t stream) {
 
 // true when the staged (integer) variant with TH rows fits LDS for this T
 template <int PREC, int NT, int TH>
-bool staged_fits(int T) {
-  return Lds<PREC, NT, TH, true>::fits && Lds<PREC, NT, TH, true>::total + dynamic_lds(T) <= kLdsLimit;
+bool staged_fits(int T, int F) {
+  return Lds<PREC, NT, TH, true>::fits && Lds<PREC, NT, TH, true>::total + dynamic_lds(T, F) <= kLdsLimit;
 }
 
 }  // namespace fused_detail

@@ -10,7 +10,7 @@ namespace bf {
 template hipError_t launch_fused_nt<BF_INST_PREC, BF_INST_NT>(const JobDesc&, int, hipStream_t);
 namespace fused_detail {
 template TileChoice choose_tile<BF_INST_PREC, BF_INST_NT>(const JobDesc&, int);
-template hipError_t launch_batched_class<BF_INST_PREC, BF_INST_NT>(const JobDesc*, const int4*, int, int,
+template hipError_t launch_batched_class<BF_INST_PREC, BF_INST_NT>(const JobDesc*, const int4*, int, int, int,
                                                                    TileChoice, int, hipStream_t);
 }  // namespace fused_detail
 }  // namespace bf

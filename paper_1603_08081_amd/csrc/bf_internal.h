@@ -33,6 +33,7 @@ struct JobDesc {
   int W;            // window half-width
   int K;            // highest harmonic
   int T;            // half-period
+  int F;            // gray-level tables cover f = 0..F (integer-input path); F >= 1
   int flags;
   float c0;         // range centring constant (T / 2)
   float w1[2 * BF_MAX_W + 1];   // unit-sum 1-D spatial profile on [-W, W]
@@ -60,7 +61,7 @@ struct TileChoice {
 TileChoice choose_tile(const JobDesc& job, bf_planes prec, int th_pref);
 // one persistent launch over n_items work items (int4: job, x0, y0, -) that
 // share window class, plane format and TileChoice; grid = workgroups
-hipError_t launch_batched(const JobDesc* jobs_dev, const int4* items_dev, int n_items, int t_max,
+hipError_t launch_batched(const JobDesc* jobs_dev, const int4* items_dev, int n_items, int t_max, int f_max,
                           bf_planes prec, int window_tiles, TileChoice tc, int grid, hipStream_t stream);
 
 // thread-local error text

@@ -79,7 +79,7 @@ struct WaveLds {
 
 // dynamic LDS: cos/sin(pi m / T) [2T x 8 B], then the modulation tables
 // [2][(T+1) x 8 B] and the demodulation tables [2][(T+1) x 8 B]
-inline size_t wave_dynamic_lds(int T) { return 32 * (size_t)(T + 1) + 16 * (size_t)T; }
+inline size_t wave_dynamic_lds(int T, int F) { return 32 * (size_t)(F + 1) + 16 * (size_t)T; }
 
 // One output tile (kWaveCols x TH at X0, Y0) of one image, all harmonics.
 // tab has room for 4 (T+1) 8-byte entries; lut holds cos/sin(pi m / T),
@@ -107,7 +107,8 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
   const float* __restrict__ src = job.src;
   const int sp = job.src_pitch;
   const float c0 = job.c0;
-  const size_t span = 8 * (size_t)(T + 1);
+  const int F = job.F;
+  const size_t span = 8 * (size_t)(F + 1);
 
   for (int m = tid; m < (build_lut ? 2 * T : 0); m += kWaveThreads) {
     double s, c;
@@ -119,7 +120,7 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
   for (int idx = tid; idx < FROWS * LWU; idx += kWaveThreads) {
     const int r = idx / LWU, c = idx - r * LWU;
     float v = src[(size_t)fold(Y0 - W + r, H) * sp + fold(X0 - Wal + c, Wd)];
-    v = fminf(fmaxf(v, 0.f), (float)T);  // NaN -> 0; the flag promises integers in [0, T]
+    v = fminf(fmaxf(v, 0.f), (float)F);  // NaN -> 0; the flag promises integers in [0, F]
     const int f = (int)v;
     ftile[r][c] = (uint16_t)(f * MODB);
     if constexpr (FP16) vtile[r][c] = (_Float16)((float)f - c0);
@@ -154,7 +155,7 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
     unsigned char* tm = tmod_k(kk);
     unsigned char* td = tdem_k(kk);
     const float dkf = (float)job.d[kk];
-    for (int f = tid; f <= T; f += kWaveThreads) {
+    for (int f = tid; f <= F; f += kWaveThreads) {
       const float m = reduce_2t((float)kk * (float)f, pt);
       const float2 cs = lut[min(max((int)m, 0), 2 * T - 1)];
       const uint32_t w0 = PT::bits(cs.x) | (PT::bits(cs.y) << 16);
@@ -372,14 +373,15 @@ __global__ void __launch_bounds__(kWaveThreads) BF_WAVE_OCC wave_batched_kernel(
 }
 
 template <int PREC, int NT, int TH>
-bool wave_fits(int T) {
-  return kWaveBuildable<PREC, NT, TH> && WaveLds<PREC, NT, TH>::total + wave_dynamic_lds(T) <= kLdsLimit;
+bool wave_fits(int T, int F) {
+  return kWaveBuildable<PREC, NT, TH> && WaveLds<PREC, NT, TH>::total + wave_dynamic_lds(T, F) <= kLdsLimit;
 }
 
 template <int PREC, int NT, int TH>
 hipError_t launch_wave(const JobDesc& job, hipStream_t stream) {
   dim3 grid((job.width + kWaveCols - 1) / kWaveCols, (job.height + TH - 1) / TH);
-  hipLaunchKernelGGL((wave_kernel<PREC, NT, TH>), grid, dim3(kWaveThreads), wave_dynamic_lds(job.T), stream, job);
+  hipLaunchKernelGGL((wave_kernel<PREC, NT, TH>), grid, dim3(kWaveThreads), wave_dynamic_lds(job.T, job.F), stream,
+                     job);
   return hipGetLastError();
 }
 
@@ -389,9 +391,9 @@ template <int NT>
 constexpr bool kWaveTall = NT <= 4;
 
 template <int PREC, int NT, int TH>
-bool wave_ok(int T) {
+bool wave_ok(int T, int F) {
   if constexpr (TH == 128 && !kWaveTall<NT>) return false;
-  else return wave_fits<PREC, NT, TH>(T);
+  else return wave_fits<PREC, NT, TH>(T, F);
 }
 
 // Calls fn(integral_constant<int, TH>) for a wave-kernel tile height.
@@ -413,20 +415,20 @@ TileChoice choose_tile(const JobDesc& job, int th_pref) {
   const bool integer = (job.flags & BF_FLAG_INTEGER_INPUT) != 0;
   if constexpr (PREC != BF_PLANES_FP32) {
     if (integer) {
-      if (th_pref >= 128 && wave_ok<PREC, NT, 128>(job.T)) return TileChoice{kWaveCols, 128, 1};
-      if (th_pref >= 64 && wave_ok<PREC, NT, 64>(job.T)) return TileChoice{kWaveCols, 64, 1};
-      if (wave_ok<PREC, NT, 32>(job.T)) return TileChoice{kWaveCols, 32, 1};
+      if (th_pref >= 128 && wave_ok<PREC, NT, 128>(job.T, job.F)) return TileChoice{kWaveCols, 128, 1};
+      if (th_pref >= 64 && wave_ok<PREC, NT, 64>(job.T, job.F)) return TileChoice{kWaveCols, 64, 1};
+      if (wave_ok<PREC, NT, 32>(job.T, job.F)) return TileChoice{kWaveCols, 32, 1};
     }
   } else if (integer) {
-    if (th_pref >= 64 && staged_fits<PREC, NT, 64>(job.T)) return TileChoice{Geo<PREC, NT>::COLS, 64, 2};
-    if (staged_fits<PREC, NT, 32>(job.T)) return TileChoice{Geo<PREC, NT>::COLS, 32, 2};
+    if (th_pref >= 64 && staged_fits<PREC, NT, 64>(job.T, job.F)) return TileChoice{Geo<PREC, NT>::COLS, 64, 2};
+    if (staged_fits<PREC, NT, 32>(job.T, job.F)) return TileChoice{Geo<PREC, NT>::COLS, 32, 2};
   }
   return TileChoice{Geo<PREC, NT>::COLS, 32, 0};
 }
 
 // One persistent launch over `n_items` items of one (family, TH) class.
 template <int PREC, int NT>
-hipError_t launch_batched_class(const JobDesc* jobs, const int4* items, int n_items, int t_max,
+hipError_t launch_batched_class(const JobDesc* jobs, const int4* items, int n_items, int t_max, int f_max,
                                 TileChoice tc, int grid, hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
   auto fit_grid = [&](const void* fn, int threads, size_t dyn) {
@@ -443,10 +445,10 @@ hipError_t launch_batched_class(const JobDesc* jobs, const int4* items, int n_it
     if constexpr (PREC == BF_PLANES_FP32) {
       return hipErrorInvalidValue;
     } else {
-      const size_t dyn = wave_dynamic_lds(t_max);
+      const size_t dyn = wave_dynamic_lds(t_max, f_max);
       return with_wave_rows<NT>(tc.th, [&](auto th_c) -> hipError_t {
         constexpr int TH = decltype(th_c)::value;
-        if (!wave_ok<PREC, NT, TH>(t_max)) return hipErrorInvalidConfiguration;
+        if (!wave_ok<PREC, NT, TH>(t_max, f_max)) return hipErrorInvalidConfiguration;
         const int g = fit_grid(reinterpret_cast<const void*>(&wave_batched_kernel<PREC, NT, TH>), kWaveThreads, dyn);
         hipLaunchKernelGGL((wave_batched_kernel<PREC, NT, TH>), dim3(g), dim3(kWaveThreads), dyn, stream,
                            jobs, items, n_items, t_max);
@@ -454,7 +456,7 @@ hipError_t launch_batched_class(const JobDesc* jobs, const int4* items, int n_it
       });
     }
   }
-  const size_t dyn = dynamic_lds(t_max);
+  const size_t dyn = dynamic_lds(t_max, f_max);
   auto go = [&](auto th_c, auto int_c) -> hipError_t {
     constexpr int TH = decltype(th_c)::value;
     constexpr bool INT = decltype(int_c)::value;
@@ -490,8 +492,8 @@ hipError_t launch_fused_nt(const JobDesc& job, int th, hipStream_t stream) {
         return with_wave_rows<NT>(tc.th, [&](auto th_c) { return launch_wave<PREC, NT, decltype(th_c)::value>(job, stream); });
     }
   } else if (integer) {
-    if (th > 32 && staged_fits<PREC, NT, 64>(job.T)) return launch_t<PREC, NT, 64, true>(job, stream);
-    if (staged_fits<PREC, NT, 32>(job.T)) return launch_t<PREC, NT, 32, true>(job, stream);
+    if (th > 32 && staged_fits<PREC, NT, 64>(job.T, job.F)) return launch_t<PREC, NT, 64, true>(job, stream);
+    if (staged_fits<PREC, NT, 32>(job.T, job.F)) return launch_t<PREC, NT, 32, true>(job, stream);
   }
   // general path; its per-pixel phase needs more registers, so 32-row tiles
   return launch_t<PREC, NT, 32, false>(job, stream);

@@ -47,7 +47,7 @@ class bf_job(ctypes.Structure):
         ("phi_table", ctypes.POINTER(ctypes.c_double)),
         ("T", ctypes.c_int), ("eps", ctypes.c_double), ("K_max", ctypes.c_int),
         ("d", ctypes.POINTER(ctypes.c_double)), ("K", ctypes.c_int),
-        ("flags", ctypes.c_int),
+        ("flags", ctypes.c_int), ("f_max", ctypes.c_int),
     ]
 
 
@@ -99,6 +99,10 @@ def _load():
     lib.bf_plan_describe.restype = I
     lib.bf_plan_destroy.argtypes = [P]
     lib.bf_plan_destroy.restype = None
+    lib.bf_dynamic_range_workspace_bytes.argtypes = [I, I]
+    lib.bf_dynamic_range_workspace_bytes.restype = Z
+    lib.bf_dynamic_range.argtypes = [P, I, I, I, I, P, P, Z, P]
+    lib.bf_dynamic_range.restype = I
     lib.bf_last_error.argtypes = []
     lib.bf_last_error.restype = ctypes.c_char_p
     hip = sorted(p for p in _hip_runtimes() if "libamdhip64" in p)
@@ -143,7 +147,7 @@ class Job:
 
     def __init__(self, src, dst, *, spatial="gaussian", sigma_s=1.0, W=-1, range_kind="gaussian",
                  sigma_r=30.0, T=255, eps=1e-2, K_max=None, d=None, phi_table=None,
-                 integer_input=False, height=None, width=None, src_pitch=None, dst_pitch=None):
+                 integer_input=False, f_max=0, height=None, width=None, src_pitch=None, dst_pitch=None):
         self._keep = []
         s = bf_job()
         s.src = _ptr(src)
@@ -170,6 +174,7 @@ class Job:
             s.d = dd.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             s.K = len(dd) - 1
         s.flags = BF_FLAG_INTEGER_INPUT if integer_input else 0
+        s.f_max = int(f_max)
         self.struct = s
 
 
@@ -266,3 +271,20 @@ class Plan:
             self.destroy()
         except Exception:
             pass
+
+
+def bf_dynamic_range_workspace_bytes(height: int, width: int) -> int:
+    n = lib.bf_dynamic_range_workspace_bytes(int(height), int(width))
+    if n == ctypes.c_size_t(-1).value:
+        raise BfError(BF_E_INVALID, "height and width must be >= 1")
+    return int(n)
+
+
+def bf_dynamic_range(src, W: int, T_out, workspace, ws_bytes: int, stream=None, height=None, width=None,
+                     src_pitch=None) -> int:
+    """bf_dynamic_range: the local dynamic range of a device image into the
+    device int T_out (asynchronous)."""
+    h, w = _hw(src) if height is None else (height, width)
+    pitch = int(src_pitch if src_pitch is not None else _pitch(src, w))
+    return _check(lib.bf_dynamic_range(_ptr(src), int(h), int(w), pitch, int(W), _ptr(T_out), _ptr(workspace),
+                                       int(ws_bytes), _stream_handle(stream)))

@@ -203,3 +203,34 @@ def test_plan_describe_lists_classes():
     with pytest.raises(native.BfError):
         pl.tune(stream=0)     # not uploaded yet
     pl.destroy()
+
+
+def test_dynamic_range_rejects_bad_arguments_before_device_work():
+    ws = native.bf_dynamic_range_workspace_bytes(64, 80)
+    assert ws >= 4 * 64 * 80
+    cases = [
+        (dict(src=None), native.BF_E_INVALID),
+        (dict(W=-1), native.BF_E_INVALID),
+        (dict(W=65), native.BF_E_INVALID),
+        (dict(height=0), native.BF_E_INVALID),
+        (dict(src_pitch=10), native.BF_E_INVALID),
+        (dict(T_out=None), native.BF_E_INVALID),
+        (dict(workspace=None), native.BF_E_WORKSPACE),
+        (dict(ws_bytes=ws - 1), native.BF_E_WORKSPACE),
+        (dict(workspace=0x30000004), native.BF_E_WORKSPACE),
+    ]
+    for kw, code in cases:
+        a = dict(src=FAKE_SRC, height=64, width=80, src_pitch=80, W=5, T_out=FAKE_DST, workspace=0x30000000,
+                 ws_bytes=ws)
+        a.update(kw)
+        rc = native.lib.bf_dynamic_range(a["src"], a["height"], a["width"], a["src_pitch"], a["W"], a["T_out"],
+                                         a["workspace"], a["ws_bytes"], None)
+        assert rc == code, (kw, rc)
+    with pytest.raises(native.BfError):
+        native.bf_dynamic_range_workspace_bytes(0, 5)
+
+
+def test_f_max_validated():
+    with pytest.raises(native.BfError) as ei:
+        native.bf_filter(_job(f_max=2000), "fp32", stream=0)
+    assert ei.value.code == native.BF_E_INVALID
