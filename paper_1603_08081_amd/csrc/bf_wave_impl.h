@@ -52,6 +52,10 @@ constexpr int kWaveCols = 16 * kWaveNW;          // output columns per tile
 #ifndef BF_WAVE_HOIST_REGS
 #define BF_WAVE_HOIST_REGS 0
 #endif
+// read the next row-pass step's gray-level offsets one step ahead
+#ifndef BF_WAVE_PREFETCH
+#define BF_WAVE_PREFETCH 1
+#endif
 // optional register budget of the wave kernels (waves per SIMD)
 #ifdef BF_WAVE_MIN_WAVES
 #define BF_WAVE_OCC __attribute__((amdgpu_waves_per_eu(BF_WAVE_MIN_WAVES)))
@@ -201,8 +205,23 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
     auto run = [&](auto nplc) {
       constexpr int NPL = decltype(nplc)::value;  // 1 for k = 0 (plane f - c0 only), else 4
       typename PT::V4 ring[NT][NPL];
+      // gray-level offsets of the row-pass operands, read one step ahead so
+      // that the LDS latency of the next step hides behind this one
+      constexpr bool PF = BF_WAVE_PREFETCH && !HOIST;
+      uint4 fq_pf[2][PF ? KS : 1];
+      if constexpr (PF) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+          fq_pf[0][ks] = *reinterpret_cast<const uint4*>(&ftile[n16][16 * wave + 32 * ks + 8 * g]);
+      }
       static_for<0, NS>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
+        if constexpr (PF && s + 1 < NS) {
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks)
+            fq_pf[(s + 1) & 1][ks] =
+                *reinterpret_cast<const uint4*>(&ftile[16 * (s + 1) + n16][16 * wave + 32 * ks + 8 * g]);
+        }
         // ---- row pass of step s: operands gathered straight into registers
         f32x4 racc[NPL];
         for (int pi = 0; pi < NPL; ++pi) racc[pi] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -220,6 +239,7 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
           if constexpr (NPL == 4) {
             uint4 fq;
             if constexpr (HOIST) fq = fq_h[s][ks];
+            else if constexpr (PF) fq = fq_pf[s & 1][ks];
             else fq = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
             const uint32_t fw[4] = {fq.x, fq.y, fq.z, fq.w};
             uint32_t pc[4], ps[4], pfc[4], pfs[4];
@@ -257,6 +277,7 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
             } else {
               uint4 fq;
               if constexpr (HOIST) fq = fq_h[s][ks];
+              else if constexpr (PF) fq = fq_pf[s & 1][ks];
               else fq = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
               const uint32_t fw[4] = {fq.x, fq.y, fq.z, fq.w};
               uint32_t pv[4];
