@@ -11,18 +11,15 @@
 // drift freely and the matrix, vector and LDS work of different waves
 // overlaps.
 //
-// Per harmonic k and gray level f the tables hold, for float16 planes,
-// (cos, sin)(k w f) as an fp16 pair -- the (f - c0) cos and (f - c0) sin
-// planes are then formed with packed fp16 multiplies against a staged tile
-// of f - c0 (exact in fp16 for half-integers) -- and, for bfloat16 planes,
-// the four plane values rounded to bfloat16.  The demodulation table holds
-// d_k cos and d_k sin in fp32.
+// Per harmonic k and gray level f the modulation table holds the four plane
+// values cos, sin, (f - c0) cos and (f - c0) sin of k w f, each rounded once
+// to the plane format (8 bytes); the demodulation table holds d_k cos and
+// d_k sin in fp32.  A row-pass operand is one 8-byte gather per pixel and
+// two byte permutes per pixel pair and plane pair.
 #include "bf_fused_impl.h"
 
 namespace bf {
 namespace fused_detail {
-
-typedef _Float16 h2v __attribute__((ext_vector_type(2)));
 
 // (low 16 bits of a) | (low 16 bits of b) << 16, and the same for the high
 // halves: one byte permute each (v_perm_b32 takes its second source as
@@ -41,17 +38,6 @@ constexpr int kWaveNW = BF_WAVE_NW;              // waves per workgroup
 constexpr int kWaveThreads = 64 * kWaveNW;
 constexpr int kWaveCols = 16 * kWaveNW;          // output columns per tile
 
-// float16 planes can take (f - c0) cos / sin from packed fp16 multiplies
-// against a staged (f - c0) tile (1) or from 8-byte tables like bfloat16 (0);
-// the tables need half the LDS per tile.
-#ifndef BF_WAVE_PKMUL
-#define BF_WAVE_PKMUL 0
-#endif
-// registers (per lane) the wave kernel may spend on keeping the staged
-// row-pass operands of a whole tile across harmonics
-#ifndef BF_WAVE_HOIST_REGS
-#define BF_WAVE_HOIST_REGS 0
-#endif
 // read the next row-pass step's gray-level offsets one step ahead
 #ifndef BF_WAVE_PREFETCH
 #define BF_WAVE_PREFETCH 1
@@ -65,19 +51,18 @@ constexpr int kWaveCols = 16 * kWaveNW;          // output columns per tile
 
 template <int PREC, int NT>
 struct WaveGeo {
-  static constexpr bool FP16 = (PREC == BF_PLANES_FP16) && BF_WAVE_PKMUL;
   static constexpr int KS = (NT + 1) / 2;
   static constexpr int LWU = 16 * (kWaveNW - 1) + 32 * KS;  // staged input columns
-  static constexpr int FW = LWU + 8;                         // padded row (u16 / fp16)
-  static constexpr int MODB = FP16 ? 4 : 8;                  // modulation-table entry bytes
+  static constexpr int FW = LWU + 8;                         // padded row (u16)
+  static constexpr int MODB = 8;                             // modulation-table entry bytes
 };
 
-// LDS use of one tile of TH rows: gray-level offsets (and f - c0 for fp16)
+// LDS use of one tile of TH rows: the gray-level table offsets of the staged tile
 template <int PREC, int NT, int TH>
 struct WaveLds {
   using G = WaveGeo<PREC, NT>;
   static constexpr int FROWS = 16 * (TH / 16 + NT - 1);
-  static constexpr size_t tile = (size_t)FROWS * G::FW * 2 * (G::FP16 ? 2 : 1);
+  static constexpr size_t tile = (size_t)FROWS * G::FW * 2;
   static constexpr size_t total = tile + 4 * (2 * BF_MAX_W + 1) + 64;
 };
 
@@ -86,21 +71,18 @@ struct WaveLds {
 inline size_t wave_dynamic_lds(int T, int F) { return 32 * (size_t)(F + 1) + 16 * (size_t)T; }
 
 // One output tile (kWaveCols x TH at X0, Y0) of one image, all harmonics.
-// tab has room for 4 (T+1) 8-byte entries; lut holds cos/sin(pi m / T),
+// tab has room for 4 (F+1) 8-byte entries; lut holds cos/sin(pi m / T),
 // rebuilt here when build_lut is set.  Every thread of the workgroup must
 // call it (it contains barriers).
 template <int PREC, int NT, int TH>
-__device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, uint16_t* ftile_raw,
-                                          _Float16* vtile_raw, float* w1s, unsigned char* tab,
-                                          float2* lut, bool build_lut) {
+__device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, uint16_t* ftile_raw, float* w1s,
+                                          unsigned char* tab, float2* lut, bool build_lut) {
   using G = WaveGeo<PREC, NT>;
   using PT = Planes<PREC>;
   using E = typename PT::E;
-  constexpr bool FP16 = G::FP16;
   constexpr int KS = G::KS, LWU = G::LWU, FW = G::FW, MODB = G::MODB;
   constexpr int NJ = TH / 16, NS = NJ + NT - 1, FROWS = 16 * NS;
   auto ftile = reinterpret_cast<uint16_t(*)[FW]>(ftile_raw);
-  auto vtile = reinterpret_cast<_Float16(*)[FW]>(vtile_raw);
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, g = lane >> 4, n16 = lane & 15;
@@ -120,14 +102,13 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
     lut[m] = make_float2((float)c, (float)s);
   }
   for (int t = tid; t <= 2 * W; t += kWaveThreads) w1s[t] = job.w1[t];
-  // stage the haloed tile once: folded borders, f clamped to [0, T]
+  // stage the haloed tile once: folded borders, f clamped to [0, F]
   for (int idx = tid; idx < FROWS * LWU; idx += kWaveThreads) {
     const int r = idx / LWU, c = idx - r * LWU;
     float v = src[(size_t)fold(Y0 - W + r, H) * sp + fold(X0 - Wal + c, Wd)];
     v = fminf(fmaxf(v, 0.f), (float)F);  // NaN -> 0; the flag promises integers in [0, F]
     const int f = (int)v;
     ftile[r][c] = (uint16_t)(f * MODB);
-    if constexpr (FP16) vtile[r][c] = (_Float16)((float)f - c0);
   }
   __syncthreads();
 
@@ -162,37 +143,13 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
     for (int f = tid; f <= F; f += kWaveThreads) {
       const float m = reduce_2t((float)kk * (float)f, pt);
       const float2 cs = lut[min(max((int)m, 0), 2 * T - 1)];
+      const float v = (float)f - c0;
       const uint32_t w0 = PT::bits(cs.x) | (PT::bits(cs.y) << 16);
-      if constexpr (FP16) {
-        *reinterpret_cast<uint32_t*>(tm + MODB * f) = w0;
-      } else {
-        const float v = (float)f - c0;
-        const uint32_t w1 = PT::bits(v * cs.x) | (PT::bits(v * cs.y) << 16);
-        *reinterpret_cast<uint2*>(tm + MODB * f) = make_uint2(w0, w1);
-      }
+      const uint32_t w1 = PT::bits(v * cs.x) | (PT::bits(v * cs.y) << 16);
+      *reinterpret_cast<uint2*>(tm + MODB * f) = make_uint2(w0, w1);
       *reinterpret_cast<float2*>(td + 8 * f) = make_float2(dkf * cs.x, dkf * cs.y);
     }
   };
-  // demodulation table offset of gray level f from its modulation offset
-  auto dem_off = [](uint32_t off) { return FP16 ? off * 2 : off; };
-
-  // The staged tile does not change across harmonics: when the operands of
-  // all row-pass steps fit the register budget, read them from LDS once.
-  constexpr bool HOIST = NS * KS * (FP16 ? 8 : 4) <= BF_WAVE_HOIST_REGS;
-  constexpr int HS = HOIST ? NS : 1, HK = HOIST ? KS : 1, HV = (HOIST && FP16) ? NS : 1;
-  uint4 fq_h[HS][HK], vq_h[HV][HK];
-  if constexpr (HOIST) {
-#pragma unroll
-    for (int s2 = 0; s2 < NS; ++s2)
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const int rr = 16 * s2 + n16, cc = 16 * wave + 32 * ks + 8 * g;
-        fq_h[s2][ks] = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
-        if constexpr (FP16) vq_h[s2][ks] = *reinterpret_cast<const uint4*>(&vtile[rr][cc]);
-      }
-  }
-  (void)fq_h;
-  (void)vq_h;
 
   build(0);
   if (K >= 1) build(1);
@@ -207,7 +164,7 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
       typename PT::V4 ring[NT][NPL];
       // gray-level offsets of the row-pass operands, read one step ahead so
       // that the LDS latency of the next step hides behind this one
-      constexpr bool PF = BF_WAVE_PREFETCH && !HOIST;
+      constexpr bool PF = BF_WAVE_PREFETCH;
       uint4 fq_pf[2][PF ? KS : 1];
       if constexpr (PF) {
 #pragma unroll
@@ -229,38 +186,20 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
         for (int ks = 0; ks < KS; ++ks) {
           const int rr = 16 * s + n16, cc = 16 * wave + 32 * ks + 8 * g;
           typename PT::V8 a;
-          uint32_t vq[4];
-          if constexpr (FP16) {
-            uint4 v4;
-            if constexpr (HOIST) v4 = vq_h[s][ks];
-            else v4 = *reinterpret_cast<const uint4*>(&vtile[rr][cc]);
-            vq[0] = v4.x; vq[1] = v4.y; vq[2] = v4.z; vq[3] = v4.w;
-          }
+          uint4 fq;
+          if constexpr (PF) fq = fq_pf[s & 1][ks];
+          else fq = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
+          const uint32_t fw[4] = {fq.x, fq.y, fq.z, fq.w};  // table offsets of pixels 2h, 2h + 1
           if constexpr (NPL == 4) {
-            uint4 fq;
-            if constexpr (HOIST) fq = fq_h[s][ks];
-            else if constexpr (PF) fq = fq_pf[s & 1][ks];
-            else fq = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
-            const uint32_t fw[4] = {fq.x, fq.y, fq.z, fq.w};
             uint32_t pc[4], ps[4], pfc[4], pfs[4];
 #pragma unroll
             for (int h = 0; h < 4; ++h) {  // pixels 2h, 2h + 1
-              if constexpr (FP16) {
-                const uint32_t ta = *reinterpret_cast<const uint32_t*>(tm + (fw[h] & 0xffffu));
-                const uint32_t tb = *reinterpret_cast<const uint32_t*>(tm + (fw[h] >> 16));
-                pc[h] = lo_halves(ta, tb);
-                ps[h] = hi_halves(ta, tb);
-                const h2v vv = __builtin_bit_cast(h2v, vq[h]);
-                pfc[h] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(h2v, pc[h]) * vv);
-                pfs[h] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(h2v, ps[h]) * vv);
-              } else {
-                const uint2 ta = *reinterpret_cast<const uint2*>(tm + (fw[h] & 0xffffu));
-                const uint2 tb = *reinterpret_cast<const uint2*>(tm + (fw[h] >> 16));
-                pc[h] = lo_halves(ta.x, tb.x);
-                ps[h] = hi_halves(ta.x, tb.x);
-                pfc[h] = lo_halves(ta.y, tb.y);
-                pfs[h] = hi_halves(ta.y, tb.y);
-              }
+              const uint2 ta = *reinterpret_cast<const uint2*>(tm + (fw[h] & 0xffffu));
+              const uint2 tb = *reinterpret_cast<const uint2*>(tm + (fw[h] >> 16));
+              pc[h] = lo_halves(ta.x, tb.x);
+              ps[h] = hi_halves(ta.x, tb.x);
+              pfc[h] = lo_halves(ta.y, tb.y);
+              pfs[h] = hi_halves(ta.y, tb.y);
             }
             __builtin_memcpy(&a, pc, 16);
             racc[0] = PT::mma(a, brow[ks], racc[0]);
@@ -272,23 +211,14 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
             racc[3] = PT::mma(a, brow[ks], racc[3]);
           } else {
             // harmonic 0: the single plane f - c0
-            if constexpr (FP16) {
-              __builtin_memcpy(&a, vq, 16);
-            } else {
-              uint4 fq;
-              if constexpr (HOIST) fq = fq_h[s][ks];
-              else if constexpr (PF) fq = fq_pf[s & 1][ks];
-              else fq = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
-              const uint32_t fw[4] = {fq.x, fq.y, fq.z, fq.w};
-              uint32_t pv[4];
+            uint32_t pv[4];
 #pragma unroll
-              for (int h = 0; h < 4; ++h) {
-                const float va = (float)((fw[h] & 0xffffu) / MODB) - c0;
-                const float vb = (float)((fw[h] >> 16) / MODB) - c0;
-                pv[h] = PT::bits(va) | (PT::bits(vb) << 16);
-              }
-              __builtin_memcpy(&a, pv, 16);
+            for (int h = 0; h < 4; ++h) {
+              const float va = (float)((fw[h] & 0xffffu) / MODB) - c0;
+              const float vb = (float)((fw[h] >> 16) / MODB) - c0;
+              pv[h] = PT::bits(va) | (PT::bits(vb) << 16);
             }
+            __builtin_memcpy(&a, pv, 16);
             racc[0] = PT::mma(a, brow[ks], racc[0]);
           }
         }
@@ -320,7 +250,7 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
             const uint32_t off[4] = {fo[j][0] & 0xffffu, fo[j][0] >> 16, fo[j][1] & 0xffffu, fo[j][1] >> 16};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const float2 t = *reinterpret_cast<const float2*>(td + dem_off(off[i]));
+              const float2 t = *reinterpret_cast<const float2*>(td + off[i]);
               P[j][i] = fmaf(t.x, fb[2][i], fmaf(t.y, fb[3][i], P[j][i]));
               Q[j][i] = fmaf(t.x, fb[0][i], fmaf(t.y, fb[1][i], Q[j][i]));
             }
@@ -360,10 +290,9 @@ __global__ void __launch_bounds__(kWaveThreads) BF_WAVE_OCC wave_kernel(const Jo
   if constexpr (kWaveBuildable<PREC, NT, TH>) {
     constexpr size_t TILE_ELEMS = WaveLds<PREC, NT, TH>::FROWS * WaveGeo<PREC, NT>::FW;
     __shared__ __attribute__((aligned(16))) uint16_t ftile[TILE_ELEMS];
-    __shared__ __attribute__((aligned(16))) _Float16 vtile[WaveGeo<PREC, NT>::FP16 ? TILE_ELEMS : 8];
     __shared__ float w1s[2 * BF_MAX_W + 1];
     extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
-    wave_tile<PREC, NT, TH>(job, blockIdx.x * kWaveCols, blockIdx.y * TH, ftile, vtile, w1s,
+    wave_tile<PREC, NT, TH>(job, blockIdx.x * kWaveCols, blockIdx.y * TH, ftile, w1s,
                             dyn + 16 * (size_t)job.T, reinterpret_cast<float2*>(dyn), true);
   }
 }
@@ -378,7 +307,6 @@ __global__ void __launch_bounds__(kWaveThreads) BF_WAVE_OCC wave_batched_kernel(
   if constexpr (kWaveBuildable<PREC, NT, TH>) {
     constexpr size_t TILE_ELEMS = WaveLds<PREC, NT, TH>::FROWS * WaveGeo<PREC, NT>::FW;
     __shared__ __attribute__((aligned(16))) uint16_t ftile[TILE_ELEMS];
-    __shared__ __attribute__((aligned(16))) _Float16 vtile[WaveGeo<PREC, NT>::FP16 ? TILE_ELEMS : 8];
     __shared__ float w1s[2 * BF_MAX_W + 1];
     extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
     float2* lut = reinterpret_cast<float2*>(dyn);
@@ -387,7 +315,7 @@ __global__ void __launch_bounds__(kWaveThreads) BF_WAVE_OCC wave_batched_kernel(
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
       const int4 w = items[it];
       const JobDesc& job = jobs[w.x];
-      wave_tile<PREC, NT, TH>(job, w.y, w.z, ftile, vtile, w1s, tab, lut, job.T != lut_t);
+      wave_tile<PREC, NT, TH>(job, w.y, w.z, ftile, w1s, tab, lut, job.T != lut_t);
       lut_t = job.T;
     }
   }
