@@ -224,3 +224,28 @@ def test_sampled_range_kernels(name):
     if r.E < w0:
         dire = oracle.direct(f, "gaussian", 4.0, 12, "table", T=T, table=phi)
         assert np.abs(out - dire).max() <= oracle.accuracy_bound(T, r.E, w0) + 0.5
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("W", [48, 64])
+def test_16bit_widest_windows(prec, W):
+    f = polygon_image(150, 141, seed=W + 1)
+    r = _fit("gaussian", 30.0, eps=1e-3)
+    out, _ = gpu_filter(f, prec, spatial="gaussian", sigma_s=W / 3.0, W=W, T=255, d=r.d, integer_input=True)
+    ref = oracle.fourier(f, "gaussian", W / 3.0, W, r.d, 255)
+    err = np.abs(out - ref).max()
+    _report("16-bit wide %s W=%d" % (prec, W), err)
+    assert err < (0.5 if prec == "fp16" else 4.0)
+
+
+def test_largest_T_and_K():
+    """T = BF_MAX_T (1024 gray levels) and K = BF_MAX_K (255 harmonics)."""
+    f = np.rint(polygon_image(120, 133, seed=77) * (1024.0 / 255.0)).astype(np.float32)
+    r = oracle.fit_kernel("gaussian", 4.0, 1024, 0.0, 255)
+    assert r.K == 255
+    for prec, tol in (("fp32", TOL_FP32), ("fp16", 0.5 * 1024 / 255)):
+        out, _ = gpu_filter(f, prec, spatial="gaussian", sigma_s=3.0, W=9, T=1024, d=r.d, integer_input=True)
+        ref = oracle.fourier(f, "gaussian", 3.0, 9, r.d, 1024)
+        err = np.abs(out - ref).max()
+        _report("T=1024 K=255 %s" % prec, err)
+        assert err <= tol
