@@ -236,6 +236,22 @@ typedef struct bf_plan bf_plan;
  */
 int bf_plan_tune(bf_plan* plan, void* hip_stream, int reps);
 int bf_plan_describe(const bf_plan* plan, char* buf, size_t len);
+
+/*
+ * The tuner's remembered choices, shared by the process, can be kept across
+ * processes in a small text file ("bf-tune 1", then one line per entry:
+ * planes, window class, family, round(log2(pixels)), tile rows, grid mode).
+ * bf_tune_save   writes every entry; BF_OK or BF_E_INVALID (path).
+ * bf_tune_load   merges a file's entries (a file's entry replaces the same
+ *                key); returns the number of entries read (>= 0), or
+ *                BF_E_INVALID for an unreadable or malformed file (nothing
+ *                merged then).
+ * bf_tune_clear  forgets every entry.
+ * Plans created afterwards start from the remembered geometry.  Host-only.
+ */
+int bf_tune_save(const char* path);
+int bf_tune_load(const char* path);
+void bf_tune_clear(void);
 int bf_plan_create(const bf_job* jobs, int n_jobs, bf_planes prec, bf_plan** plan);
 size_t bf_plan_workspace_bytes(const bf_plan* plan);
 int bf_plan_upload(bf_plan* plan, void* workspace, size_t ws_bytes, void* hip_stream);

@@ -27,6 +27,8 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <map>
 #include <mutex>
 #include <string>
@@ -582,4 +584,51 @@ extern "C" int bf_plan_describe(const bf_plan* plan, char* buf, size_t len) {
     buf[n] = '\0';
   }
   return static_cast<int>(out.size());
+}
+
+// ---- persistence of the tuned geometry -------------------------------------
+// Text file: a header line "bf-tune 1", then one line per entry:
+//   planes window_class family round(log2(pixels)) tile_rows grid
+extern "C" int bf_tune_save(const char* path) {
+  if (!path) return fail(BF_E_INVALID, "path is NULL");
+  std::ofstream out(path, std::ios::trunc);
+  if (!out) return fail(BF_E_INVALID, std::string("cannot write ") + path);
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  out << "bf-tune 1\n";
+  for (const auto& kv : *g_tune)
+    out << kv.first.prec << ' ' << kv.first.nt << ' ' << kv.first.family << ' ' << kv.first.size_log2 << ' '
+        << kv.second.th << ' ' << kv.second.grid << '\n';
+  if (!out) return fail(BF_E_INVALID, std::string("write failed: ") + path);
+  return BF_OK;
+}
+
+extern "C" int bf_tune_load(const char* path) {
+  if (!path) return fail(BF_E_INVALID, "path is NULL");
+  std::ifstream in(path);
+  if (!in) return fail(BF_E_INVALID, std::string("cannot read ") + path);
+  std::string line;
+  if (!std::getline(in, line) || line != "bf-tune 1") return fail(BF_E_INVALID, "not a bf-tune 1 file");
+  std::map<TuneKey, TuneVal> entries;
+  int lineno = 1;
+  while (std::getline(in, line)) {
+    ++lineno;
+    if (line.empty()) continue;
+    std::istringstream ls(line);
+    TuneKey k{};
+    TuneVal v{};
+    std::string rest;
+    if (!(ls >> k.prec >> k.nt >> k.family >> k.size_log2 >> v.th >> v.grid) || (ls >> rest) ||
+        k.prec < 0 || k.prec > 2 || k.nt < 2 || k.nt > 9 || k.family < 0 || k.family > 2 ||
+        (v.th != 32 && v.th != 64 && v.th != 128) || v.grid < -1)
+      return fail(BF_E_INVALID, std::string("bad entry on line ") + std::to_string(lineno) + " of " + path);
+    entries[k] = v;
+  }
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  for (const auto& kv : entries) (*g_tune)[kv.first] = kv.second;
+  return static_cast<int>(entries.size());
+}
+
+extern "C" void bf_tune_clear(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  g_tune->clear();
 }

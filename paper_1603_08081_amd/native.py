@@ -97,6 +97,12 @@ def _load():
     lib.bf_plan_tune.restype = I
     lib.bf_plan_describe.argtypes = [P, ctypes.c_char_p, Z]
     lib.bf_plan_describe.restype = I
+    lib.bf_tune_save.argtypes = [ctypes.c_char_p]
+    lib.bf_tune_save.restype = I
+    lib.bf_tune_load.argtypes = [ctypes.c_char_p]
+    lib.bf_tune_load.restype = I
+    lib.bf_tune_clear.argtypes = []
+    lib.bf_tune_clear.restype = None
     lib.bf_plan_destroy.argtypes = [P]
     lib.bf_plan_destroy.restype = None
     lib.bf_dynamic_range_workspace_bytes.argtypes = [I, I]
@@ -288,3 +294,16 @@ def bf_dynamic_range(src, W: int, T_out, workspace, ws_bytes: int, stream=None, 
     pitch = int(src_pitch if src_pitch is not None else _pitch(src, w))
     return _check(lib.bf_dynamic_range(_ptr(src), int(h), int(w), pitch, int(W), _ptr(T_out), _ptr(workspace),
                                        int(ws_bytes), _stream_handle(stream)))
+
+
+def bf_tune_save(path: str) -> int:
+    return _check(lib.bf_tune_save(os.fsencode(path)))
+
+
+def bf_tune_load(path: str) -> int:
+    """Merge a saved tuning file; returns the number of entries read."""
+    return _check(lib.bf_tune_load(os.fsencode(path)))
+
+
+def bf_tune_clear() -> None:
+    lib.bf_tune_clear()

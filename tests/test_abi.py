@@ -234,3 +234,28 @@ def test_f_max_validated():
     with pytest.raises(native.BfError) as ei:
         native.bf_filter(_job(f_max=2000), "fp32", stream=0)
     assert ei.value.code == native.BF_E_INVALID
+
+
+def test_tune_cache_round_trip(tmp_path):
+    native.bf_tune_clear()
+    p = tmp_path / "tune.txt"
+    # fp16, window class 2 (W = 3), wave kernel, 64 x 64 = 2^12 pixels
+    p.write_text("bf-tune 1\n1 2 1 12 32 -1\n")
+    assert native.bf_tune_load(str(p)) == 1
+    pl = native.Plan([_job(W=3, sigma_s=1.0, integer_input=True)], "fp16")
+    c = pl.describe()["classes"][0]
+    assert (c["nt"], c["family"], c["tile_rows"], c["grid"], c["tuned"]) == (2, 1, 32, -1, True)
+    pl.destroy()
+    q = tmp_path / "saved.txt"
+    native.bf_tune_save(str(q))
+    assert q.read_text() == "bf-tune 1\n1 2 1 12 32 -1\n"
+    native.bf_tune_clear()
+    pl = native.Plan([_job(W=3, sigma_s=1.0, integer_input=True)], "fp16")
+    assert not pl.describe()["classes"][0]["tuned"]
+    pl.destroy()
+    for bad in ("nonsense\n", "bf-tune 1\n1 2 1 12 48 0\n", "bf-tune 1\n1 2 1 12 32\n", "bf-tune 1\n7 2 1 12 32 0\n"):
+        p.write_text(bad)
+        with pytest.raises(native.BfError):
+            native.bf_tune_load(str(p))
+    with pytest.raises(native.BfError):
+        native.bf_tune_load(str(tmp_path / "missing.txt"))

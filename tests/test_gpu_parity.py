@@ -249,3 +249,20 @@ def test_largest_T_and_K():
         err = np.abs(out - ref).max()
         _report("T=1024 K=255 %s" % prec, err)
         assert err <= tol
+
+
+@pytest.mark.parametrize("shape,W", [((1, 77), 0), ((77, 1), 0), ((2, 300), 1), ((300, 2), 1), ((3, 5), 2),
+                                     ((45, 77), 44), ((61, 53), 52)])
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_thin_images_and_window_near_image_size(shape, W, prec):
+    H, Wd = shape
+    f = polygon_image(max(H, 8), max(Wd, 8), seed=H * 31 + Wd)[:H, :Wd].copy()
+    r = _fit("gaussian", 25.0, eps=1e-3)
+    out, _ = gpu_filter(f, prec, spatial="gaussian", sigma_s=max(W / 3.0, 0.5), W=W, T=255, d=r.d,
+                        integer_input=True)
+    ref = oracle.fourier(f, "gaussian", max(W / 3.0, 0.5), W, r.d, 255)
+    err = np.abs(out - ref).max()
+    _report("thin %s W=%d %s" % (shape, W, prec), err)
+    assert err <= (TOL_FP32 if prec == "fp32" else 0.5)
+    if W == 0:   # a one-pixel window returns the image
+        assert np.abs(out - f).max() <= (1e-4 if prec == "fp32" else 0.5)
