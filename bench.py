@@ -210,12 +210,14 @@ def main():
         params = [dict(spatial=wl["spatial"], sigma_s=sp["sigma_s"], W=sp["W"], range_kind=sp["range_kind"],
                        sigma_r=sp["sigma_r"]) for sp in batch_specs(wl["n"], wl["seed"])[:n]]
     fits = {}
+    t_fit = time.time()
     for p in params:
         key = (p["range_kind"], p["sigma_r"])
         if key not in fits:
             fits[key] = native.bf_fit_coeffs(key[0], key[1], wl["T"], wl["eps"], wl["K_max"])[1]
         p["d"] = fits[key]
         p["K"] = len(p["d"]) - 1
+    fit_ms = (time.time() - t_fit) * 1e3 / len(fits)
     dev = torch.device("cuda", 0)
     srcs = [torch.from_numpy(f).to(dev) for f in imgs]
     dst = [torch.empty_like(x) for x in srcs]
@@ -277,7 +279,7 @@ def main():
     value = px / (ms * 1e-3) / 1e6
     log("%s planes: %.3f ms/step, %.1f Mpix/s (plan, graph replay)" % (args.precision, ms, value))
 
-    extra = {}
+    extra = {"host_fit_ms_per_kernel": round(fit_ms, 3)}
     ms_call = timed_call(args.precision, dst, max(2, args.steps // 2))
     log("%s planes: %.3f ms/step through bf_filter_batched" % (args.precision, ms_call))
     extra["batched_call_ms_per_step"] = round(ms_call, 3)
