@@ -232,6 +232,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     plans = {}
+    medians = {}
 
     def timed(prec, out, steps, warmup, use_graph=True):
         """Device time per step of one plan launch (graph replay by default)
@@ -249,15 +250,18 @@ def main():
         for _ in range(warmup):
             plan.launch(stream, use_graph)
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(steps):
+        # one event between consecutive steps: the total gives the mean, the
+        # gaps give the per-step median
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record(stream)
+        for i in range(steps):
             plan.launch(stream, use_graph)
-        e1.record(stream)
+            ev[i + 1].record(stream)
         torch.cuda.synchronize()
         plan.destroy()
-        return e0.elapsed_time(e1) / steps
+        per_step = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+        medians[prec] = per_step[steps // 2] if steps % 2 else 0.5 * (per_step[steps // 2 - 1] + per_step[steps // 2])
+        return ev[0].elapsed_time(ev[steps]) / steps
 
     def timed_call(prec, out, steps):
         """Device time per step of bf_filter_batched (job table copy included)."""
@@ -279,7 +283,7 @@ def main():
     value = px / (ms * 1e-3) / 1e6
     log("%s planes: %.3f ms/step, %.1f Mpix/s (plan, graph replay)" % (args.precision, ms, value))
 
-    extra = {"host_fit_ms_per_kernel": round(fit_ms, 3)}
+    extra = {"host_fit_ms_per_kernel": round(fit_ms, 3), "median_ms_per_step": round(medians[args.precision], 3)}
     ms_call = timed_call(args.precision, dst, max(2, args.steps // 2))
     log("%s planes: %.3f ms/step through bf_filter_batched" % (args.precision, ms_call))
     extra["batched_call_ms_per_step"] = round(ms_call, 3)
