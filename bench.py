@@ -181,7 +181,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the path shards by whole images or by "
+        print("bench.py measures one GPU only (the path shards by whole images or by "
               "row stripes with W-row halos; no multi-GPU run is implemented); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)

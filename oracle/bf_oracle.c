@@ -89,7 +89,7 @@ static double phi_series(const double* d, int K, int T, double t) {
 }
 
 /*
- * Shared driver: evaluates eq. (1) or eq. (9) at the requested pixels.
+ * Shared routine: evaluates eq. (1) or eq. (9) at the requested pixels.
  * mode 0: true kernel phi; mode 1: cosine series phi_K.
  * pix (length npix) lists linear output indices r * width + c; NULL means
  * every pixel in row-major order (npix is then ignored).
