@@ -220,7 +220,7 @@ typedef struct bf_plan bf_plan;
 /*
  * bf_plan_tune    autotuner: for every kernel class of an uploaded plan,
  *                 times `reps` launches of each tile height the class's
- *                 jobs support (32, 64, and 128 rows for narrow windows) with
+ *                 jobs support (32, 64, and 96 or 128 rows for narrow windows) with
  *                 both grid modes (a persistent grid sized by occupancy, or
  *                 one workgroup per tile), keeps the fastest, re-uploads the
  *                 table and remembers the choice for later plans of this

@@ -78,12 +78,14 @@ int grid_mode_from_env() {
   return v > 0 ? v : 0;
 }
 
-// Preferred output-tile height (32, 64 or 128 rows) from BF_TILE_ROWS; 0 = default.
+bool valid_tile_rows(int v) { return v == 32 || v == 64 || v == 96 || v == 128; }
+
+// Preferred output-tile height (32, 64, 96 or 128 rows) from BF_TILE_ROWS; 0 = default.
 int tile_rows_from_env() {
   const char* s = std::getenv("BF_TILE_ROWS");
   if (!s || !*s) return 0;
   const int v = std::atoi(s);
-  return (v == 32 || v == 64 || v == 128) ? v : 0;
+  return valid_tile_rows(v) ? v : 0;
 }
 
 int valid_prec(bf_planes prec) {
@@ -158,7 +160,7 @@ int build_plan(const bf_job* jobs, int n_jobs, bf_planes prec, PlanData& p) {
       c.nt = nt;
       c.family = base.family;
       c.tc = base;
-      for (int th : {32, 64, 128}) {
+      for (int th : {32, 64, 96, 128}) {
         const TileChoice t = choose_tile(r.desc, prec, th);
         if (t.th == th && t.family == base.family) c.th_options.push_back(th);
       }
@@ -619,7 +621,7 @@ extern "C" int bf_tune_load(const char* path) {
     std::string rest;
     if (!(ls >> k.prec >> k.nt >> k.family >> k.size_log2 >> v.th >> v.grid) || (ls >> rest) ||
         k.prec < 0 || k.prec > 2 || k.nt < 2 || k.nt > 9 || k.family < 0 || k.family > 2 ||
-        (v.th != 32 && v.th != 64 && v.th != 128) || v.grid < -1)
+        !valid_tile_rows(v.th) || v.grid < -1)
       return fail(BF_E_INVALID, std::string("bad entry on line ") + std::to_string(lineno) + " of " + path);
     entries[k] = v;
   }

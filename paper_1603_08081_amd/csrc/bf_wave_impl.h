@@ -42,6 +42,10 @@ constexpr int kWaveCols = 16 * kWaveNW;          // output columns per tile
 #ifndef BF_WAVE_PREFETCH
 #define BF_WAVE_PREFETCH 1
 #endif
+// also issue the next step's table gathers before this step's permutes
+#ifndef BF_WAVE_GATHER_AHEAD
+#define BF_WAVE_GATHER_AHEAD 1
+#endif
 // optional register budget of the wave kernels (waves per SIMD)
 #ifdef BF_WAVE_MIN_WAVES
 #define BF_WAVE_OCC __attribute__((amdgpu_waves_per_eu(BF_WAVE_MIN_WAVES)))
@@ -165,19 +169,40 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
       // gray-level offsets of the row-pass operands, read one step ahead so
       // that the LDS latency of the next step hides behind this one
       constexpr bool PF = BF_WAVE_PREFETCH;
+      // with GPF the table gathers of step s + 1 are also issued before the
+      // permutes and MFMAs of step s (two buffers of gathered entries)
+      constexpr bool GPF = PF && BF_WAVE_GATHER_AHEAD && NPL == 4;
       uint4 fq_pf[2][PF ? KS : 1];
-      if constexpr (PF) {
+      uint2 gd[GPF ? 2 : 1][GPF ? KS : 1][8];
+      auto load_fq = [&](int buf, int step) {
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
-          fq_pf[0][ks] = *reinterpret_cast<const uint4*>(&ftile[n16][16 * wave + 32 * ks + 8 * g]);
+          fq_pf[buf][ks] = *reinterpret_cast<const uint4*>(&ftile[16 * step + n16][16 * wave + 32 * ks + 8 * g]);
+      };
+      auto gather = [&](int buf) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const uint4 fq = fq_pf[buf][ks];
+          const uint32_t fw[4] = {fq.x, fq.y, fq.z, fq.w};
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            gd[buf][ks][2 * h] = *reinterpret_cast<const uint2*>(tm + (fw[h] & 0xffffu));
+            gd[buf][ks][2 * h + 1] = *reinterpret_cast<const uint2*>(tm + (fw[h] >> 16));
+          }
+        }
+      };
+      if constexpr (PF) load_fq(0, 0);
+      if constexpr (GPF) {
+        gather(0);
+        if (NS > 1) load_fq(1, 1);
       }
       static_for<0, NS>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
-        if constexpr (PF && s + 1 < NS) {
-#pragma unroll
-          for (int ks = 0; ks < KS; ++ks)
-            fq_pf[(s + 1) & 1][ks] =
-                *reinterpret_cast<const uint4*>(&ftile[16 * (s + 1) + n16][16 * wave + 32 * ks + 8 * g]);
+        if constexpr (GPF) {
+          if constexpr (s + 1 < NS) gather((s + 1) & 1);
+          if constexpr (s + 2 < NS) load_fq(s & 1, s + 2);
+        } else if constexpr (PF && s + 1 < NS) {
+          load_fq((s + 1) & 1, s + 1);
         }
         // ---- row pass of step s: operands gathered straight into registers
         f32x4 racc[NPL];
@@ -186,16 +211,22 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
         for (int ks = 0; ks < KS; ++ks) {
           const int rr = 16 * s + n16, cc = 16 * wave + 32 * ks + 8 * g;
           typename PT::V8 a;
-          uint4 fq;
-          if constexpr (PF) fq = fq_pf[s & 1][ks];
-          else fq = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
-          const uint32_t fw[4] = {fq.x, fq.y, fq.z, fq.w};  // table offsets of pixels 2h, 2h + 1
           if constexpr (NPL == 4) {
             uint32_t pc[4], ps[4], pfc[4], pfs[4];
 #pragma unroll
             for (int h = 0; h < 4; ++h) {  // pixels 2h, 2h + 1
-              const uint2 ta = *reinterpret_cast<const uint2*>(tm + (fw[h] & 0xffffu));
-              const uint2 tb = *reinterpret_cast<const uint2*>(tm + (fw[h] >> 16));
+              uint2 ta, tb;
+              if constexpr (GPF) {
+                ta = gd[s & 1][ks][2 * h];
+                tb = gd[s & 1][ks][2 * h + 1];
+              } else {
+                uint4 fq;
+                if constexpr (PF) fq = fq_pf[s & 1][ks];
+                else fq = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
+                const uint32_t fw[4] = {fq.x, fq.y, fq.z, fq.w};  // table offsets of pixels 2h, 2h + 1
+                ta = *reinterpret_cast<const uint2*>(tm + (fw[h] & 0xffffu));
+                tb = *reinterpret_cast<const uint2*>(tm + (fw[h] >> 16));
+              }
               pc[h] = lo_halves(ta.x, tb.x);
               ps[h] = hi_halves(ta.x, tb.x);
               pfc[h] = lo_halves(ta.y, tb.y);
@@ -211,6 +242,10 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
             racc[3] = PT::mma(a, brow[ks], racc[3]);
           } else {
             // harmonic 0: the single plane f - c0
+            uint4 fq;
+            if constexpr (PF) fq = fq_pf[s & 1][ks];
+            else fq = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
+            const uint32_t fw[4] = {fq.x, fq.y, fq.z, fq.w};
             uint32_t pv[4];
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
@@ -334,14 +369,14 @@ hipError_t launch_wave(const JobDesc& job, hipStream_t stream) {
   return hipGetLastError();
 }
 
-// 128-row tiles keep their P, Q accumulators in registers without spilling
-// only for the narrower window classes
+// 96- and 128-row tiles (more output rows per halo row) are built only for
+// the narrower window classes, where their accumulators fit the registers
 template <int NT>
 constexpr bool kWaveTall = NT <= 4;
 
 template <int PREC, int NT, int TH>
 bool wave_ok(int T, int F) {
-  if constexpr (TH == 128 && !kWaveTall<NT>) return false;
+  if constexpr (TH > 64 && !kWaveTall<NT>) return false;
   else return wave_fits<PREC, NT, TH>(T, F);
 }
 
@@ -350,6 +385,7 @@ template <int NT, class F>
 hipError_t with_wave_rows(int th, F&& fn) {
   if constexpr (kWaveTall<NT>) {
     if (th == 128) return fn(std::integral_constant<int, 128>{});
+    if (th == 96) return fn(std::integral_constant<int, 96>{});
   }
   if (th == 64) return fn(std::integral_constant<int, 64>{});
   if (th == 32) return fn(std::integral_constant<int, 32>{});
@@ -365,6 +401,7 @@ TileChoice choose_tile(const JobDesc& job, int th_pref) {
   if constexpr (PREC != BF_PLANES_FP32) {
     if (integer) {
       if (th_pref >= 128 && wave_ok<PREC, NT, 128>(job.T, job.F)) return TileChoice{kWaveCols, 128, 1};
+      if (th_pref >= 96 && wave_ok<PREC, NT, 96>(job.T, job.F)) return TileChoice{kWaveCols, 96, 1};
       if (th_pref >= 64 && wave_ok<PREC, NT, 64>(job.T, job.F)) return TileChoice{kWaveCols, 64, 1};
       if (wave_ok<PREC, NT, 32>(job.T, job.F)) return TileChoice{kWaveCols, 32, 1};
     }
