@@ -46,10 +46,6 @@ constexpr int kWaveCols = 16 * kWaveNW;          // output columns per tile
 #ifndef BF_WAVE_GATHER_AHEAD
 #define BF_WAVE_GATHER_AHEAD 1
 #endif
-// read the demodulation offsets of each output tile from LDS when needed
-#ifndef BF_WAVE_FO_LDS
-#define BF_WAVE_FO_LDS 0
-#endif
 // optional register budget of the wave kernels (waves per SIMD)
 #ifdef BF_WAVE_MIN_WAVES
 #define BF_WAVE_OCC __attribute__((amdgpu_waves_per_eu(BF_WAVE_MIN_WAVES)))
@@ -130,20 +126,12 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
   double wsum = 0.0;
   for (int t = -W; t <= W; ++t) wsum += (double)wq(t);
   const float q0 = (float)(job.d[0] * wsum * wsum);
-  // table byte offsets of this lane's output pixels (two per register) in
-  // output tile j: kept in registers, or read from the staged tile when
-  // needed (which frees 2 NJ registers for the tall tiles)
-  constexpr bool FO_REGS = !BF_WAVE_FO_LDS;
-  uint32_t fo[FO_REGS ? NJ : 1][2];
-  auto fo_of = [&](int j) {
-    return *reinterpret_cast<const uint2*>(&ftile[W + 16 * j + n16][Wal + 16 * wave + 4 * g]);
-  };
-  if constexpr (FO_REGS) {
-    for (int j = 0; j < NJ; ++j) {
-      const uint2 q = fo_of(j);
-      fo[j][0] = q.x;
-      fo[j][1] = q.y;
-    }
+  // table byte offsets of this lane's output pixels, two per register
+  uint32_t fo[NJ][2];
+  for (int j = 0; j < NJ; ++j) {
+    const uint2 q = *reinterpret_cast<const uint2*>(&ftile[W + 16 * j + n16][Wal + 16 * wave + 4 * g]);
+    fo[j][0] = q.x;
+    fo[j][1] = q.y;
   }
   float P[NJ][4], Q[NJ][4];
   for (int j = 0; j < NJ; ++j)
@@ -294,10 +282,7 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
             for (int i = 0; i < 4; ++i) fb[pi][i] = acc[i];
           }
           if constexpr (NPL == 4) {
-            uint2 q;
-            if constexpr (FO_REGS) q = make_uint2(fo[j][0], fo[j][1]);
-            else q = fo_of(j);
-            const uint32_t off[4] = {q.x & 0xffffu, q.x >> 16, q.y & 0xffffu, q.y >> 16};
+            const uint32_t off[4] = {fo[j][0] & 0xffffu, fo[j][0] >> 16, fo[j][1] & 0xffffu, fo[j][1] >> 16};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const float2 t = *reinterpret_cast<const float2*>(td + off[i]);
