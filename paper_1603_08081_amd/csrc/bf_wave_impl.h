@@ -369,10 +369,11 @@ hipError_t launch_wave(const JobDesc& job, hipStream_t stream) {
   return hipGetLastError();
 }
 
-// 96- and 128-row tiles (more output rows per halo row) are built only for
-// the narrower window classes, where their accumulators fit the registers
+// 96- and 128-row tiles (more output rows per halo row) are built for windows
+// up to W = 48; they may spill a few dozen registers to scratch, which costs
+// less than the latency their longer software pipeline hides
 template <int NT>
-constexpr bool kWaveTall = NT <= 4;
+constexpr bool kWaveTall = NT <= 7;
 
 template <int PREC, int NT, int TH>
 bool wave_ok(int T, int F) {
