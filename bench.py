@@ -43,13 +43,14 @@ def alg_flops_per_px(K, W):
 
 
 def kernel_sources_digest():
-    """sha256 over the library's kernel and host sources (byte counters taken
-    on other sources no longer describe the kernel)."""
+    """sha256 over the sources the kernels are compiled from (the HIP files
+    and the headers they include; byte counters taken on other sources no
+    longer describe the kernel).  Host-only .cpp files are not part of it."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1603_08081_amd", "csrc")
     h = hashlib.sha256()
     for fn in sorted(os.listdir(csrc)):
-        if fn.endswith((".h", ".hip", ".cpp")):
+        if fn.endswith((".h", ".hip")):
             h.update(fn.encode())
             with open(os.path.join(csrc, fn), "rb") as fh:
                 h.update(fh.read())

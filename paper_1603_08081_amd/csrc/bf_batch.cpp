@@ -208,6 +208,44 @@ int build_plan(const bf_job* jobs, int n_jobs, bf_planes prec, PlanData& p) {
     p.classes.push_back(std::move(c));
   }
   if (max_items > (size_t)INT32_MAX) return fail(BF_E_UNSUPPORTED, "too many tiles in one batch");
+  // every job's output must be disjoint from every other job's input and
+  // output: the launches write all images concurrently
+  {
+    struct Span {
+      uintptr_t lo, hi;
+      int job;
+      bool out;
+    };
+    std::vector<Span> spans;
+    spans.reserve(2 * (size_t)n_jobs);
+    for (int i = 0; i < n_jobs; ++i) {
+      const JobDesc& d = p.descs[i];
+      const uintptr_t s0 = reinterpret_cast<uintptr_t>(d.src), d0 = reinterpret_cast<uintptr_t>(d.dst);
+      spans.push_back({s0, s0 + sizeof(float) * ((size_t)(d.height - 1) * d.src_pitch + d.width), i, false});
+      spans.push_back({d0, d0 + sizeof(float) * ((size_t)(d.height - 1) * d.dst_pitch + d.width), i, true});
+    }
+    std::sort(spans.begin(), spans.end(), [](const Span& a, const Span& b) { return a.lo < b.lo; });
+    // sweep: an output span may not intersect any other span (inputs may
+    // share memory with inputs)
+    size_t best_out = SIZE_MAX;  // index of the open output span reaching farthest
+    uintptr_t reach_any = 0, reach_out = 0;
+    int job_any = -1;
+    for (size_t k = 0; k < spans.size(); ++k) {
+      const Span& sp = spans[k];
+      const bool hits_out = best_out != SIZE_MAX && sp.lo < reach_out && spans[best_out].job != sp.job;
+      const bool out_hits_any = sp.out && sp.lo < reach_any && job_any != sp.job;
+      if (hits_out || out_hits_any)
+        return fail(BF_E_INVALID, "job " + std::to_string(sp.job) + ": an output overlaps another job's image");
+      if (sp.hi > reach_any) {
+        reach_any = sp.hi;
+        job_any = sp.job;
+      }
+      if (sp.out && sp.hi > reach_out) {
+        reach_out = sp.hi;
+        best_out = k;
+      }
+    }
+  }
   emit_items(p);
   // most expensive class first: when launched one after another its tail is
   // followed by cheaper work

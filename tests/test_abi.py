@@ -136,12 +136,12 @@ def test_unknown_precision_rejected():
 
 def test_workspace_query_for_valid_jobs():
     assert native.bf_workspace_bytes([_job()], "fp32") >= 0
-    assert native.bf_workspace_bytes([_job(), _job(W=-1, sigma_s=2.0)], "fp16") >= 0
+    assert native.bf_workspace_bytes([_job(), _job(W=-1, sigma_s=2.0, dst=FAKE_DST + (1 << 20))], "fp16") >= 0
 
 
 def test_batched_workspace_grows_with_jobs_and_tiles():
     one = native.bf_workspace_bytes([_job()], "fp16")
-    two = native.bf_workspace_bytes([_job(), _job()], "fp16")
+    two = native.bf_workspace_bytes([_job(), _job(dst=FAKE_DST + (1 << 20))], "fp16")
     assert 0 < one < two
     big = native.bf_workspace_bytes([_job(height=2000, width=3000, src_pitch=3000, dst_pitch=3000,
                                           dst=FAKE_DST + (1 << 26))], "fp16")
@@ -151,7 +151,7 @@ def test_batched_workspace_grows_with_jobs_and_tiles():
 
 
 def test_plan_host_side_without_device_work():
-    pl = native.Plan([_job(), _job(W=-1, sigma_s=2.0)], "fp16")
+    pl = native.Plan([_job(), _job(W=-1, sigma_s=2.0, dst=FAKE_DST + (1 << 20))], "fp16")
     assert pl.status == native.BF_OK
     assert pl.workspace_bytes() == native.bf_workspace_bytes(pl.jobs, "fp16")
     # launch before upload, and uploads into a missing or small workspace, fail before any HIP call
@@ -188,7 +188,7 @@ def test_plan_reports_unconverged_fit_and_rejects_bad_jobs():
 def test_plan_describe_lists_classes():
     jobs = [_job(), _job(W=30, sigma_s=10.0, height=200, width=300, src_pitch=300, dst_pitch=300,
                          dst=FAKE_DST + (1 << 24)),
-            _job(integer_input=True)]
+            _job(integer_input=True, dst=FAKE_DST + (1 << 25))]
     pl = native.Plan(jobs, "fp16")
     info = pl.describe()
     assert info["jobs"] == 3 and info["planes"] == native.PLANES["fp16"]
@@ -259,3 +259,23 @@ def test_tune_cache_round_trip(tmp_path):
             native.bf_tune_load(str(p))
     with pytest.raises(native.BfError):
         native.bf_tune_load(str(tmp_path / "missing.txt"))
+
+
+def test_batched_rejects_outputs_that_overlap_other_jobs():
+    a = dict(height=64, width=64)
+    # two jobs reading the same image into different outputs: allowed
+    ok = [_job(**a), _job(dst=FAKE_DST + (1 << 20), **a)]
+    assert native.bf_workspace_bytes(ok, "fp16") > 0
+    # two jobs writing the same output
+    bad = [_job(**a), _job(src=FAKE_SRC + (1 << 20), **a)]
+    with pytest.raises(native.BfError) as ei:
+        native.bf_workspace_bytes(bad, "fp16")
+    assert ei.value.code == native.BF_E_INVALID and "overlaps another job" in native.bf_last_error()
+    # job 1 writes into job 0's input
+    bad = [_job(**a), _job(src=FAKE_SRC + (1 << 21), dst=FAKE_SRC + 4 * 100, **a)]
+    with pytest.raises(native.BfError):
+        native.Plan(bad, "fp32")
+    # job 0's output runs into job 1's input further up in memory
+    bad = [_job(dst=FAKE_DST, **a), _job(src=FAKE_DST + 4 * 64 * 63, dst=FAKE_DST + (1 << 22), **a)]
+    with pytest.raises(native.BfError):
+        native.bf_filter_batched(bad, "fp32", stream=0)
