@@ -183,6 +183,9 @@ int bf_filter(const bf_job* job, bf_planes prec, void* workspace, size_t ws_byte
  * 16-byte aligned, owned by the caller) on `hip_stream`, asynchronously, from
  * library-owned pinned memory; the caller must not reuse the workspace for
  * anything else until the stream has passed the launches.
+ * Inside a stream capture the table copy becomes a copy node of the
+ * caller's graph; its pinned staging buffer is then reserved for that graph
+ * and never reused.
  * Returns the first error found (nothing is enqueued then), else
  * BF_FIT_NOT_CONVERGED if any job's fit stopped at K_max, else BF_OK.
  */
