@@ -172,6 +172,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-tune", action="store_true", help="skip the plan autotuner (bf_plan_tune)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="file of remembered tuner choices: loaded before planning if it exists, "
+                         "written after tuning")
     ap.add_argument("--eager", action="store_true",
                     help="launch the plan eagerly instead of replaying its HIP graph")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -231,6 +234,8 @@ def main():
                            integer_input=True) for i, p in enumerate(params)]
 
     stream = torch.cuda.current_stream()
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        log("tune cache: %d entries from %s" % (native.bf_tune_load(args.tune_cache), args.tune_cache))
 
     plans = {}
     medians = {}
@@ -247,6 +252,8 @@ def main():
             t0 = time.time()
             plan.tune(stream, reps=2)
             log("%s: tuned in %.2fs: %s" % (prec, time.time() - t0, plan.describe()["classes"]))
+            if args.tune_cache:
+                native.bf_tune_save(args.tune_cache)
         plans[prec] = plan.describe()
         for _ in range(warmup):
             plan.launch(stream, use_graph)
