@@ -296,3 +296,44 @@ def test_tune_keeps_bits_and_is_remembered(prec):
         assert torch.equal(a, b), "cached geometry, job %d" % i
     plan.destroy()
     plan2.destroy()
+
+
+def test_frames32_tuned_plan_as_benchmarked():
+    """The 32-frame UHD workload in the configuration the benchmark times: one
+    tuned plan over all frames, graph replay; every pixel of sampled rows
+    (borders, window edges, middle, seeded random) of the first, a middle and
+    the last frame against eq. (9) in FP64: float16 planes < 0.5, float32
+    planes <= 1e-3, bfloat16 reported."""
+    torch = _torch()
+    from paper_1603_08081_amd import native
+    wl = WORKLOADS["frames32_2160x3840"]
+    imgs = workload_images("frames32_2160x3840")
+    st, d, _, _ = native.bf_fit_coeffs(wl["range_kind"], wl["sigma_r"], wl["T"], wl["eps"], wl["K_max"])
+    srcs = [torch.from_numpy(f).cuda() for f in imgs]
+    stream = torch.cuda.current_stream()
+    worst = {}
+    for prec in ("fp16", "fp32", "bf16"):
+        outs = [torch.full_like(x, -1.0) for x in srcs]
+        jobs = [native.Job(x, y, spatial="gaussian", sigma_s=wl["sigma_s"], W=wl["W"], T=wl["T"], d=d,
+                           integer_input=True) for x, y in zip(srcs, outs)]
+        plan = native.Plan(jobs, prec)
+        ws = torch.empty(plan.workspace_bytes(), dtype=torch.uint8, device="cuda")
+        plan.upload(ws, ws.numel(), stream)
+        plan.tune(stream, reps=1)
+        for o in outs:
+            o.fill_(-1.0)
+        plan.launch(stream, use_graph=True)
+        torch.cuda.synchronize()
+        print(prec, plan.describe()["classes"], flush=True)
+        worst[prec] = 0.0
+        for fi in (0, 15, 31):
+            f = imgs[fi]
+            H, Wd = f.shape
+            rows = sample_rows(H, Wd, wl["W"], n_random=3, seed=fi)
+            pix = pixels_of_rows(rows, Wd)
+            ref = oracle.fourier(f, "gaussian", wl["sigma_s"], wl["W"], d, wl["T"], pixels=pix)
+            got = outs[fi].cpu().numpy().ravel()[pix]
+            worst[prec] = max(worst[prec], float(np.abs(got - ref).max()))
+        plan.destroy()
+    print("frames32 tuned plan, worst sampled error vs eq. (9) FP64:", worst, flush=True)
+    assert worst["fp16"] < 0.5 and worst["fp32"] <= TOL_FP32 and worst["bf16"] < 4.0
