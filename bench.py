@@ -42,6 +42,19 @@ def alg_flops_per_px(K, W):
     return (4 * K + 1) * 2 * (2 * W + 1) * 2
 
 
+def issued_flops_per_px(K, W, tile_rows):
+    """MFMA flops the 16-bit wave kernel issues per output pixel: each
+    16 x 16 output block needs (NJ + NT - 1) / NJ row-pass steps of KS
+    16x16x32 products per plane and KS column-pass products per plane,
+    NT = max(2, ceil((16 + 2W) / 16)), KS = ceil(NT / 2), NJ = tile_rows / 16;
+    4 planes per harmonic k >= 1, one plane for k = 0."""
+    nt = max(2, (16 + 2 * W + 15) // 16)
+    ks = (nt + 1) // 2
+    nj = tile_rows // 16
+    per_plane = ((nj + nt - 1) / nj * ks + ks) * 2 * 16 * 16 * 32 / 256.0
+    return per_plane * (4 * K + 1)
+
+
 def kernel_sources_digest():
     """sha256 over the sources the kernels are compiled from (the HIP files
     and the headers they include; byte counters taken on other sources no
@@ -345,6 +358,11 @@ def main():
             "kernel": fam[main_family] + " (modulate + row/column MFMA Toeplitz + demodulate + divide)",
             "alg_flops_per_px": round(alg_flops / px, 1), "launches_per_step": launches,
             "plan": plans[args.precision]["classes"]}
+    if launches == 1 and main_family == 1 and uniform:
+        th = plans[args.precision]["classes"][0]["tile_rows"]
+        ifl = issued_flops_per_px(params[0]["K"], params[0]["W"], th)
+        roof["issued_flops_per_px"] = round(ifl, 1)
+        roof["issued_frac"] = round(ifl * px / (ms * 1e-3) / 1e12 / peak, 4)
     if roof["traffic"] is not None:
         roof["hbm_gbs"] = round(roof["traffic"] / avg_launch_s / 1e9, 1)
         roof["hbm_frac"] = round(roof["hbm_gbs"] / PEAK_HBM_GBS, 4)
