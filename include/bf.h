@@ -72,10 +72,10 @@ typedef enum {
 } bf_planes;
 
 /* flags of bf_job.flags */
-#define BF_FLAG_INTEGER_INPUT 1 /* caller guarantees every pixel is an integer in [0, T]: enables
-                                   the exact table-only phase path.  With the flag set and a
-                                   non-integer pixel, that pixel's phase k*f is truncated to an
-                                   integer before reduction mod 2T. */
+#define BF_FLAG_INTEGER_INPUT 1 /* caller guarantees every pixel is an integer in [0, f_max]
+                                   (f_max = T unless set): enables the exact table-only phase
+                                   path.  With the flag set, a pixel outside that contract makes
+                                   the outputs whose windows contain it unspecified. */
 
 /*
  * bf_fit_coeffs -- Algorithm 2 (Sec. 3), on the host, in float64.
@@ -175,10 +175,11 @@ int bf_filter(const bf_job* job, bf_planes prec, void* workspace, size_t ws_byte
  * bf_filter_batched -- eq. (9) for n_jobs independent images of any sizes,
  * each with its own spatial window, range kernel and K.  Every job is
  * resolved on the host first (fits included); the images are cut into output
- * tiles, the tiles grouped by kernel instantiation (window class, kernel
- * family, tile height), and each group runs as ONE launch of a persistent
- * kernel whose workgroups take tiles round-robin from a list ordered by
- * decreasing cost 4K+1.  The job table and tile list are copied into
+ * tiles, the tiles grouped by kernel (window class, kernel family; each group
+ * with its own tile height), and each group runs as ONE launch of a
+ * persistent kernel whose workgroups take tiles round-robin from a list
+ * ordered by decreasing cost 4K+1.  No job's dst may overlap another job's
+ * src or dst (jobs may share a src).  The job table and tile list are copied into
  * `workspace` (device memory of at least bf_workspace_bytes() bytes,
  * 16-byte aligned, owned by the caller) on `hip_stream`, asynchronously, from
  * library-owned pinned memory; the caller must not reuse the workspace for
@@ -220,10 +221,16 @@ int bf_filter_batched(const bf_job* jobs, int n_jobs, bf_planes prec,
  *                 then frees the plan (NULL is ignored).
  */
 typedef struct bf_plan bf_plan;
+int bf_plan_create(const bf_job* jobs, int n_jobs, bf_planes prec, bf_plan** plan);
+size_t bf_plan_workspace_bytes(const bf_plan* plan);
+int bf_plan_upload(bf_plan* plan, void* workspace, size_t ws_bytes, void* hip_stream);
+int bf_plan_launch(bf_plan* plan, void* hip_stream, int use_graph);
+void bf_plan_destroy(bf_plan* plan);
+
 /*
  * bf_plan_tune    autotuner: for every kernel class of an uploaded plan,
  *                 times `reps` launches of each tile height the class's
- *                 jobs support (32, 64, and 96 or 128 rows for narrow windows) with
+ *                 jobs support (32 and 64 rows; 96 and 128 for W <= 48) with
  *                 both grid modes (a persistent grid sized by occupancy, or
  *                 one workgroup per tile), keeps the fastest, re-uploads the
  *                 table and remembers the choice for later plans of this
@@ -255,11 +262,6 @@ int bf_plan_describe(const bf_plan* plan, char* buf, size_t len);
 int bf_tune_save(const char* path);
 int bf_tune_load(const char* path);
 void bf_tune_clear(void);
-int bf_plan_create(const bf_job* jobs, int n_jobs, bf_planes prec, bf_plan** plan);
-size_t bf_plan_workspace_bytes(const bf_plan* plan);
-int bf_plan_upload(bf_plan* plan, void* workspace, size_t ws_bytes, void* hip_stream);
-int bf_plan_launch(bf_plan* plan, void* hip_stream, int use_graph);
-void bf_plan_destroy(bf_plan* plan);
 
 /*
  * bf_dynamic_range -- the dynamic range T of Sec. 3 measured on the image:

@@ -226,7 +226,11 @@ int build_plan(const bf_job* jobs, int n_jobs, bf_planes prec, PlanData& p) {
     }
     std::sort(spans.begin(), spans.end(), [](const Span& a, const Span& b) { return a.lo < b.lo; });
     // sweep: an output span may not intersect any other span (inputs may
-    // share memory with inputs)
+    // share memory with inputs).  Tracking only the farthest-reaching open
+    // span suffices because resolve_job has already rejected a job whose own
+    // src and dst hulls meet: an open span of the current span's own job
+    // cannot reach past its start, so the farthest one, when it does, is
+    // another job's.
     size_t best_out = SIZE_MAX;  // index of the open output span reaching farthest
     uintptr_t reach_any = 0, reach_out = 0;
     int job_any = -1;
