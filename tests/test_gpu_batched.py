@@ -124,6 +124,34 @@ def test_grid_modes_agree(prec, grid, monkeypatch):
         assert torch.equal(a, b), "grid %r job %d" % (grid, i)
 
 
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_offset_layouts_agree(prec, monkeypatch):
+    """The 16-bit wave kernel stages gray-level table offsets either as 16-bit
+    offsets or as 32-bit LDS addresses (gray levels 0..255, tile fits LDS);
+    both layouts compute the same bits, through bf_filter and batched."""
+    torch = _torch()
+    from paper_1603_08081_amd import native
+    specs = _mixed_specs()
+    imgs = _inputs(specs)
+    srcs = [torch.from_numpy(f).cuda() for f in imgs]
+    stream = torch.cuda.current_stream()
+    outs = {}
+    for narrow in ("0", "1"):
+        monkeypatch.setenv("BF_WAVE_NARROW", narrow)
+        single = [torch.full_like(x, -1.0) for x in srcs]
+        for j in _jobs(native, specs, srcs, single):
+            native.bf_filter(j, prec, stream=stream)
+        batched = [torch.full_like(x, -1.0) for x in srcs]
+        ws, _ = _batched(native, torch, _jobs(native, specs, srcs, batched), prec, stream)
+        torch.cuda.synchronize()
+        outs[narrow] = (single, batched)
+    for i in range(len(specs)):
+        for k in range(2):
+            a, b = outs["0"][k][i], outs["1"][k][i]
+            assert torch.isfinite(a).all()
+            assert torch.equal(a, b), "job %d %s" % (i, ("single", "batched")[k])
+
+
 def test_plan_eager_and_graph_replays():
     torch = _torch()
     from paper_1603_08081_amd import native
