@@ -251,6 +251,31 @@ def test_largest_T_and_K():
         assert err <= tol
 
 
+def test_large_T_with_gray_levels_below_256():
+    """T = 1024 with pixels in 0..255 (f_max = 255): the table-address layout
+    of the 16-bit kernel with the largest cos/sin table, single image and
+    batched (128-row tiles), against eq. (9) in FP64."""
+    import torch
+
+    from paper_1603_08081_amd import native
+    f = polygon_image(300, 261, seed=91)
+    r = oracle.fit_kernel("gaussian", 60.0, 1024, 1e-3, 100)
+    ref = oracle.fourier(f, "gaussian", 8.0, 24, r.d, 1024)
+    out, _ = gpu_filter(f, "fp16", spatial="gaussian", sigma_s=8.0, W=24, T=1024, d=r.d, f_max=255,
+                        integer_input=True)
+    err = np.abs(out - ref).max()
+    _report("T=1024 f_max=255 single fp16", err)
+    assert err <= 0.5
+    x = torch.from_numpy(f).cuda()
+    y = torch.full_like(x, -1.0)
+    job = native.Job(x, y, spatial="gaussian", sigma_s=8.0, W=24, T=1024, d=r.d, f_max=255, integer_input=True)
+    n = native.bf_workspace_bytes([job], "fp16")
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+    native.bf_filter_batched([job], "fp16", ws, n, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy(), out)
+
+
 @pytest.mark.parametrize("shape,W", [((1, 77), 0), ((77, 1), 0), ((2, 300), 1), ((300, 2), 1), ((3, 5), 2),
                                      ((45, 77), 44), ((61, 53), 52)])
 @pytest.mark.parametrize("prec", ["fp32", "fp16"])
