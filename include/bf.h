@@ -289,6 +289,23 @@ int bf_dynamic_range(const float* src, int height, int width, int src_pitch, int
 /* Thread-local text describing the last non-OK status of this thread. */
 const char* bf_last_error(void);
 
+/*
+ * Environment variables (schedule only: none of them changes a result bit).
+ *   BF_TILE_ROWS=32|64|96|128  preferred output-tile height of new plans and
+ *                  batched calls (a class takes the tallest height not above
+ *                  it that all its jobs support); read at plan creation.
+ *   BF_BATCH_GRID=items|<n>    workgroups per class launch: one per tile, or
+ *                  a fixed n; unset = a persistent grid sized by occupancy;
+ *                  read at plan creation.
+ *   BF_WAVE_NARROW=1           16-bit planes on integer images: stage 16-bit
+ *                  table offsets instead of 32-bit table addresses (the
+ *                  latter are used when the gray levels fit 256 table entries
+ *                  and the tile fits LDS); read at each launch, and captured
+ *                  with a plan's graph.
+ * While either of the first two is set, remembered tuner choices are not
+ * applied at plan creation; bf_plan_tune still times and sets the geometry.
+ */
+
 #ifdef __cplusplus
 }
 #endif
