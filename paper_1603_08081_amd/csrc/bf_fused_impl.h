@@ -245,7 +245,10 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
       }
   }
   // fp32 row-pass steps holding nonzero weights: columns [Wal - W, Wal + 16 + W)
-  const int s4lo = (Wal - W) / 4, s4hi = (Wal + 16 + W + 3) / 4;
+  // uniform bounds, kept in scalar registers so that the skip tests are
+  // scalar branches
+  const int s4lo = __builtin_amdgcn_readfirstlane((Wal - W) / 4);
+  const int s4hi = __builtin_amdgcn_readfirstlane((Wal + 16 + W + 3) / 4);
   // fp32 planes accumulate P and Q in float64 (see the column pass below);
   // 16-bit planes are limited by their own rounding and accumulate in float32
   using Acc = std::conditional_t<F32, double, float>;
@@ -375,11 +378,15 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
           const int p = (NPL == 1) ? 2 : pi;
           f32x4 acc = {0.f, 0.f, 0.f, 0.f};
           if constexpr (F32) {
+            // all operand reads first (in bounds for every W of the class),
+            // so that their LDS latency overlaps; the MFMAs outside the
+            // window's column span are skipped
+            float av[NBR];
+#pragma unroll
+            for (int s4 = 0; s4 < NBR; ++s4) av[s4] = planes[b][p][n16][16 * wave + 4 * s4 + g];
 #pragma unroll
             for (int s4 = 0; s4 < NBR; ++s4)
-              if (s4 >= s4lo && s4 < s4hi)
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(planes[b][p][n16][16 * wave + 4 * s4 + g],
-                                                            brow[s4], acc, 0, 0, 0);
+              if (s4 >= s4lo && s4 < s4hi) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s4], brow[s4], acc, 0, 0, 0);
             ring[s % NT][pi] = acc;
           } else {
 #pragma unroll
