@@ -244,11 +244,6 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
         bcol16[ks][e] = (E)wq(16 * (2 * ks + (e >> 2)) + 4 * g + (e & 3) - W - n16);
       }
   }
-  // fp32 row-pass steps holding nonzero weights: columns [Wal - W, Wal + 16 + W)
-  // uniform bounds, kept in scalar registers so that the skip tests are
-  // scalar branches
-  const int s4lo = __builtin_amdgcn_readfirstlane((Wal - W) / 4);
-  const int s4hi = __builtin_amdgcn_readfirstlane((Wal + 16 + W + 3) / 4);
   // fp32 planes accumulate P and Q in float64 (see the column pass below);
   // 16-bit planes are limited by their own rounding and accumulate in float32
   using Acc = std::conditional_t<F32, double, float>;
@@ -302,12 +297,18 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
     auto run = [&](auto nplc) {
       constexpr int NPL = decltype(nplc)::value;  // 1 for k = 0 (plane f - c0 only), else 4
       RingT ring[NT][NPL];
-      static_for<0, NS>([&](auto sc) {
-        constexpr int s = decltype(sc)::value;
+      // ---- 1. modulate rows [16 sm, 16 sm + 16) of the tile into LDS buffer
+      // sm & 1, one 8-pixel chunk per thread and pass; branch-free (lanes past
+      // the last chunk repeat it, writing the same values), so that it can
+      // interleave with the MFMAs of the step it overlaps
+      auto modulate = [&](auto smc) {
+        constexpr int s = decltype(smc)::value;
         constexpr int b = s & 1;
-        // ---- 1. modulate rows [16 s, 16 s + 16) of the tile into LDS buffer b
         constexpr int CPR = LWU / 8;  // 8-pixel chunks per row
-        for (int c = tid; c < 16 * CPR; c += NTHR) {
+        constexpr int NCH = 16 * CPR;
+#pragma unroll
+        for (int it = 0; it < (NCH + NTHR - 1) / NTHR; ++it) {
+          const int c = min(tid + it * NTHR, NCH - 1);
           const int r = c / CPR, cc = c - r * CPR;
           if constexpr (INTEGER) {
             const uint4 fq = *reinterpret_cast<const uint4*>(&ftile[16 * s + r][8 * cc]);
@@ -371,6 +372,13 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
             __builtin_memcpy(&planes[b][2][r][8 * cc], vfc, sizeof(vfc));
           }
         }
+      };
+      modulate(std::integral_constant<int, 0>{});
+      static_for<0, NS>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        constexpr int b = s & 1;
+        // buffer b complete; every wave is done with step s - 1, so buffer
+        // b ^ 1 (read by its row pass) may be overwritten below
         __syncthreads();
         // ---- 2. row pass for this wave's strip
 #pragma unroll
@@ -378,15 +386,15 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
           const int p = (NPL == 1) ? 2 : pi;
           f32x4 acc = {0.f, 0.f, 0.f, 0.f};
           if constexpr (F32) {
-            // all operand reads first (in bounds for every W of the class),
-            // so that their LDS latency overlaps; the MFMAs outside the
-            // window's column span are skipped
+            // every contraction step of the class, in one branch-free block:
+            // the steps outside this window's column span have zero weights
+            // and add exact zeros, and without branches the operand reads
+            // run ahead of the MFMA chain
             float av[NBR];
 #pragma unroll
             for (int s4 = 0; s4 < NBR; ++s4) av[s4] = planes[b][p][n16][16 * wave + 4 * s4 + g];
 #pragma unroll
-            for (int s4 = 0; s4 < NBR; ++s4)
-              if (s4 >= s4lo && s4 < s4hi) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s4], brow[s4], acc, 0, 0, 0);
+            for (int s4 = 0; s4 < NBR; ++s4) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s4], brow[s4], acc, 0, 0, 0);
             ring[s % NT][pi] = acc;
           } else {
 #pragma unroll
@@ -400,6 +408,9 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
             ring[s % NT][pi] = v;
           }
         }
+        // modulation of the next step into the other buffer, overlapping
+        // this step's matrix work
+        if constexpr (s + 1 < NS) modulate(std::integral_constant<int, s + 1>{});
         // ---- 3. column pass + 4. demodulate, once the window is complete
         if constexpr (s >= NT - 1) {
           constexpr int j = s - NT + 1;
