@@ -182,6 +182,11 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
                                            unsigned char* tab, float2* lut, bool build_lut) {
   constexpr bool INTEGER = INTEGER_REQ && Lds<PREC, NT, TH, true>::fits;
   using G = Geo<PREC, NT>;
+  // FP32 planes on integer images: each lane gathers its row-pass operands
+  // (all four plane values of a pixel, one 16-byte table entry) straight
+  // from the table, so no planes go through LDS and no barrier is needed
+  // between the 16-row steps
+  constexpr bool DIRECT = G::F32 && INTEGER;
   using PT = Planes<PREC>;
   using E = typename PT::E;
   constexpr bool F32 = G::F32;
@@ -302,6 +307,7 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
       // the last chunk repeat it, writing the same values), so that it can
       // interleave with the MFMAs of the step it overlaps
       auto modulate = [&](auto smc) {
+        if constexpr (DIRECT) return;
         constexpr int s = decltype(smc)::value;
         constexpr int b = s & 1;
         constexpr int CPR = LWU / 8;  // 8-pixel chunks per row
@@ -379,8 +385,14 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
         constexpr int b = s & 1;
         // buffer b complete; every wave is done with step s - 1, so buffer
         // b ^ 1 (read by its row pass) may be overwritten below
-        __syncthreads();
+        if constexpr (!DIRECT) __syncthreads();
         // ---- 2. row pass for this wave's strip
+        float4 tv[DIRECT ? NBR : 1];
+        if constexpr (DIRECT) {
+#pragma unroll
+          for (int s4 = 0; s4 < NBR; ++s4)
+            tv[s4] = *reinterpret_cast<const float4*>(tab + ftile[16 * s + n16][16 * wave + 4 * s4 + g]);
+        }
 #pragma unroll
         for (int pi = 0; pi < NPL; ++pi) {
           const int p = (NPL == 1) ? 2 : pi;
@@ -392,7 +404,12 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
             // run ahead of the MFMA chain
             float av[NBR];
 #pragma unroll
-            for (int s4 = 0; s4 < NBR; ++s4) av[s4] = planes[b][p][n16][16 * wave + 4 * s4 + g];
+            for (int s4 = 0; s4 < NBR; ++s4) {
+              if constexpr (DIRECT)
+                av[s4] = p == 0 ? tv[s4].x : p == 1 ? tv[s4].y : p == 2 ? tv[s4].z : tv[s4].w;
+              else
+                av[s4] = planes[b][p][n16][16 * wave + 4 * s4 + g];
+            }
 #pragma unroll
             for (int s4 = 0; s4 < NBR; ++s4) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s4], brow[s4], acc, 0, 0, 0);
             ring[s % NT][pi] = acc;
