@@ -124,13 +124,13 @@ int resolve_job(const bf_job* j, Resolved* out) {
 }
 
 int pick_tile_rows(const JobDesc& jd, bf_planes prec) {
-  // fp32 planes with wide windows need too many registers for 64-row tiles
-  if (prec == BF_PLANES_FP32 && window_tiles(jd.W) >= 5) return 32;
-  // the tallest tile that still gives every CU about one workgroup (128
-  // rows only exist for 16-bit planes and narrow windows; choose_tile falls
-  // back to 64 elsewhere)
+  // fp32 planes with windows wider than 6 row tiles (W > 40) spill registers
+  // at taller tiles
+  if (prec == BF_PLANES_FP32 && window_tiles(jd.W) >= 7) return 32;
+  // the tallest tile that still gives every CU about one workgroup
+  // (choose_tile falls back to a shorter one where a height does not exist)
   const long col_blocks = (jd.width + tile_cols(prec) - 1) / tile_cols(prec);
-  if (prec != BF_PLANES_FP32 && col_blocks * ((jd.height + 127) / 128) >= 240) return 128;
+  if (col_blocks * ((jd.height + 127) / 128) >= 240) return 128;
   return col_blocks * ((jd.height + 63) / 64) >= 240 ? 64 : 32;
 }
 

@@ -182,11 +182,11 @@ int build_plan(const bf_job* jobs, int n_jobs, bf_planes prec, PlanData& p) {
     ClassLaunch c = kv.second;
     if (c.th_options.empty()) c.th_options.push_back(32);
     std::stable_sort(c.jobs.begin(), c.jobs.end(), [&](int a, int b) { return p.descs[a].K > p.descs[b].K; });
-    // default geometry: the tallest tile the class supports for 16-bit
-    // planes (128 rows for narrow windows, else 64), 64 rows for fp32 (32 with
-    // wide windows), unless the environment or an earlier tuning run says
+    // default geometry: the tallest tile the class supports (for fp32 planes
+    // 32 rows with windows wider than 6 row tiles, which spill registers at
+    // taller tiles), unless the environment or an earlier tuning run says
     // otherwise
-    int th = th_env ? th_env : prec != BF_PLANES_FP32 ? 128 : c.nt >= 5 ? 32 : 64;
+    int th = th_env ? th_env : prec != BF_PLANES_FP32 ? 128 : c.nt >= 7 ? 32 : 128;
     int grid = grid_env;
     if (!th_env && !grid_env) {
       std::lock_guard<std::mutex> lock(g_tune_mutex);

@@ -114,7 +114,9 @@ constexpr int kThreadsFor = (PREC == BF_PLANES_FP32) ? 256 : 512;
 template <int PREC, int NT, int TH, bool INTEGER>
 struct Lds {
   using G = Geo<PREC, NT>;
-  static constexpr size_t planes = 2ull * 4 * 16 * G::LW * (G::F32 ? 4 : 2);
+  // FP32 planes on integer images gather their operands per lane and keep no
+  // planes in LDS
+  static constexpr size_t planes = (G::F32 && INTEGER) ? 0 : 2ull * 4 * 16 * G::LW * (G::F32 ? 4 : 2);
   static constexpr size_t tile = INTEGER ? 2ull * 16 * (TH / 16 + NT - 1) * G::FW : 16;
   static constexpr size_t total = planes + tile + 4 * (2 * BF_MAX_W + 1) + 64;
   // a staged variant must leave room for at least the T = 255 tables
@@ -307,7 +309,7 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
       // the last chunk repeat it, writing the same values), so that it can
       // interleave with the MFMAs of the step it overlaps
       auto modulate = [&](auto smc) {
-        if constexpr (DIRECT) return;
+        if constexpr (DIRECT) return;  // no LDS planes (the rest is never run)
         constexpr int s = decltype(smc)::value;
         constexpr int b = s & 1;
         constexpr int CPR = LWU / 8;  // 8-pixel chunks per row

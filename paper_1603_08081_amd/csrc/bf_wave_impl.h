@@ -713,6 +713,8 @@ TileChoice choose_tile(const JobDesc& job, int th_pref) {
       if (wave_ok<PREC, NT, 32>(job.T, job.F)) return TileChoice{kWaveCols, 32, 1};
     }
   } else if (integer) {
+    if (th_pref >= 128 && staged_fits<PREC, NT, 128>(job.T, job.F)) return TileChoice{Geo<PREC, NT>::COLS, 128, 2};
+    if (th_pref >= 96 && staged_fits<PREC, NT, 96>(job.T, job.F)) return TileChoice{Geo<PREC, NT>::COLS, 96, 2};
     if (th_pref >= 64 && staged_fits<PREC, NT, 64>(job.T, job.F)) return TileChoice{Geo<PREC, NT>::COLS, 64, 2};
     if (staged_fits<PREC, NT, 32>(job.T, job.F)) return TileChoice{Geo<PREC, NT>::COLS, 32, 2};
   }
@@ -767,6 +769,10 @@ hipError_t launch_batched_class(const JobDesc* jobs, const int4* items, int n_it
     return hipGetLastError();
   };
   if (tc.family == 2) {
+    if constexpr (PREC == BF_PLANES_FP32) {
+      if (tc.th == 128) return go(std::integral_constant<int, 128>{}, std::true_type{});
+      if (tc.th == 96) return go(std::integral_constant<int, 96>{}, std::true_type{});
+    }
     return tc.th == 64 ? go(std::integral_constant<int, 64>{}, std::true_type{})
                        : go(std::integral_constant<int, 32>{}, std::true_type{});
   }
@@ -790,6 +796,8 @@ hipError_t launch_fused_nt(const JobDesc& job, int th, hipStream_t stream) {
         return with_wave_rows<NT>(tc.th, [&](auto th_c) { return launch_wave<PREC, NT, decltype(th_c)::value>(job, stream); });
     }
   } else if (integer) {
+    if (th >= 128 && staged_fits<PREC, NT, 128>(job.T, job.F)) return launch_t<PREC, NT, 128, true>(job, stream);
+    if (th >= 96 && staged_fits<PREC, NT, 96>(job.T, job.F)) return launch_t<PREC, NT, 96, true>(job, stream);
     if (th > 32 && staged_fits<PREC, NT, 64>(job.T, job.F)) return launch_t<PREC, NT, 64, true>(job, stream);
     if (staged_fits<PREC, NT, 32>(job.T, job.F)) return launch_t<PREC, NT, 32, true>(job, stream);
   }
