@@ -230,7 +230,9 @@ void bf_plan_destroy(bf_plan* plan);
 /*
  * bf_plan_tune    autotuner: for every kernel class of an uploaded plan,
  *                 times `reps` launches of each tile height the class's
- *                 jobs support (32 and 64 rows; 96 and 128 for W <= 48) with
+ *                 jobs support (32 and 64 rows; 96 and 128 where the tile
+ *                 fits: 16-bit planes up to W = 48, fp32 planes on integer
+ *                 images) with
  *                 both grid modes (a persistent grid sized by occupancy, or
  *                 one workgroup per tile), keeps the fastest, re-uploads the
  *                 table and remembers the choice for later plans of this
