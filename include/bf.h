@@ -232,7 +232,7 @@ void bf_plan_destroy(bf_plan* plan);
  *                 times `reps` launches of each tile height the class's
  *                 jobs support (32 and 64 rows; 96 and 128 where the tile
  *                 fits: 16-bit planes up to W = 48, fp32 planes on integer
- *                 images) with
+ *                 images; 144 for 16-bit planes up to W = 48) with
  *                 both grid modes (a persistent grid sized by occupancy, or
  *                 one workgroup per tile), keeps the fastest, re-uploads the
  *                 table and remembers the choice for later plans of this
@@ -293,7 +293,7 @@ const char* bf_last_error(void);
 
 /*
  * Environment variables (schedule only: none of them changes a result bit).
- *   BF_TILE_ROWS=32|64|96|128  preferred output-tile height of new plans and
+ *   BF_TILE_ROWS=32|64|96|128|144  preferred output-tile height of new plans and
  *                  batched calls (a class takes the tallest height not above
  *                  it that all its jobs support); read at plan creation.
  *   BF_BATCH_GRID=items|<n>    workgroups per class launch: one per tile, or

@@ -78,9 +78,9 @@ int grid_mode_from_env() {
   return v > 0 ? v : 0;
 }
 
-bool valid_tile_rows(int v) { return v == 32 || v == 64 || v == 96 || v == 128; }
+bool valid_tile_rows(int v) { return v == 32 || v == 64 || v == 96 || v == 128 || v == 144; }
 
-// Preferred output-tile height (32, 64, 96 or 128 rows) from BF_TILE_ROWS; 0 = default.
+// Preferred output-tile height (32, 64, 96, 128 or 144 rows) from BF_TILE_ROWS; 0 = default.
 int tile_rows_from_env() {
   const char* s = std::getenv("BF_TILE_ROWS");
   if (!s || !*s) return 0;
@@ -160,7 +160,7 @@ int build_plan(const bf_job* jobs, int n_jobs, bf_planes prec, PlanData& p) {
       c.nt = nt;
       c.family = base.family;
       c.tc = base;
-      for (int th : {32, 64, 96, 128}) {
+      for (int th : {32, 64, 96, 128, 144}) {
         const TileChoice t = choose_tile(r.desc, prec, th);
         if (t.th == th && t.family == base.family) c.th_options.push_back(th);
       }

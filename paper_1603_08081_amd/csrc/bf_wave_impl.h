@@ -675,9 +675,10 @@ hipError_t launch_wave(const JobDesc& job, hipStream_t stream) {
   return hipGetLastError();
 }
 
-// 96- and 128-row tiles (more output rows per halo row) are built for windows
-// up to W = 48; they may spill a few dozen registers to scratch, which costs
-// less than the latency their longer software pipeline hides
+// 96-, 128- and 144-row tiles (more output rows per halo row; 144 divides
+// 2160-row frames into whole tiles) are built for windows up to W = 48; they
+// may spill a few dozen registers to scratch, which costs less than the
+// latency their longer software pipeline hides
 template <int NT>
 constexpr bool kWaveTall = NT <= 7;
 
@@ -691,6 +692,7 @@ bool wave_ok(int T, int F) {
 template <int NT, class F>
 hipError_t with_wave_rows(int th, F&& fn) {
   if constexpr (kWaveTall<NT>) {
+    if (th == 144) return fn(std::integral_constant<int, 144>{});
     if (th == 128) return fn(std::integral_constant<int, 128>{});
     if (th == 96) return fn(std::integral_constant<int, 96>{});
   }
@@ -707,6 +709,7 @@ TileChoice choose_tile(const JobDesc& job, int th_pref) {
   const bool integer = (job.flags & BF_FLAG_INTEGER_INPUT) != 0;
   if constexpr (PREC != BF_PLANES_FP32) {
     if (integer) {
+      if (th_pref >= 144 && wave_ok<PREC, NT, 144>(job.T, job.F)) return TileChoice{kWaveCols, 144, 1};
       if (th_pref >= 128 && wave_ok<PREC, NT, 128>(job.T, job.F)) return TileChoice{kWaveCols, 128, 1};
       if (th_pref >= 96 && wave_ok<PREC, NT, 96>(job.T, job.F)) return TileChoice{kWaveCols, 96, 1};
       if (th_pref >= 64 && wave_ok<PREC, NT, 64>(job.T, job.F)) return TileChoice{kWaveCols, 64, 1};
