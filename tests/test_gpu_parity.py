@@ -57,6 +57,37 @@ def test_fp32_widest_windows(W):
     assert err <= TOL_FP32
 
 
+@pytest.mark.parametrize("th", ["32", "64", "96", "128"])
+def test_fp32_wide_windows_every_tile_height(th, monkeypatch):
+    """FP32 planes at W = 40 and W = 64 (window classes 6 and 9) through the
+    batched path at every tile height a plan may take for them (the taller
+    ones spill registers to scratch), against eq. (9) in FP64."""
+    import torch
+
+    from paper_1603_08081_amd import native
+    monkeypatch.setenv("BF_TILE_ROWS", th)
+    r = _fit("gaussian", 30.0, eps=1e-3)
+    for W in (40, 64):
+        f = polygon_image(300, 150, seed=400 + W)
+        x = torch.from_numpy(f).cuda()
+        y = torch.full_like(x, -1.0)
+        job = native.Job(x, y, spatial="gaussian", sigma_s=W / 3.0, W=W, T=255, d=r.d, integer_input=True)
+        plan = native.Plan([job], "fp32")
+        try:
+            rows = [c["tile_rows"] for c in plan.describe()["classes"]]
+            n = plan.workspace_bytes()
+            ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+            plan.upload(ws, n, torch.cuda.current_stream())
+            plan.launch(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+        finally:
+            plan.destroy()
+        ref = oracle.fourier(f, "gaussian", W / 3.0, W, r.d, 255)
+        err = np.abs(y.cpu().numpy() - ref).max()
+        _report("fp32 W=%d tile rows %s (asked %s)" % (W, rows, th), err)
+        assert err <= TOL_FP32
+
+
 def test_gauss_256_full_image():
     """256 x 256, Gaussian sigma_s = 3 (W = 9), Gaussian sigma_r = 30.
 
