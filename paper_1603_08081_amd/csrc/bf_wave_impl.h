@@ -431,37 +431,36 @@ __device__ __forceinline__ void wave_tile_wide(const JobDesc& job, int X0, int Y
     constexpr uint32_t MOFF = PAR * SPAN, DOFF = (2 + PAR) * SPAN;
     typename PT::V4 ring[NT][NPL];
     constexpr bool GPF = NPL == 4;  // table gathers run one step ahead
-    uint4 fq_pf[2][KS][2];
+    // entry addresses of one step (read one step ahead) and the gathered
+    // entries of two steps (the gathers of step s + 1 are issued during step s)
+    uint4 fq_pf[KS][2];
     uint2 gd[GPF ? 2 : 1][GPF ? KS : 1][8];
-    auto load_fq = [&](int buf, int step) {
+    auto load_fq = [&](int step) {
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         const uint4* p = reinterpret_cast<const uint4*>(&ftile[16 * step + n16][16 * wave + 32 * ks + 8 * g]);
-        fq_pf[buf][ks][0] = p[0];
-        fq_pf[buf][ks][1] = p[1];
+        fq_pf[ks][0] = p[0];
+        fq_pf[ks][1] = p[1];
       }
     };
     auto gather = [&](int buf) {
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        const uint4 a0 = fq_pf[buf][ks][0], a1 = fq_pf[buf][ks][1];
+        const uint4 a0 = fq_pf[ks][0], a1 = fq_pf[ks][1];
         const uint32_t fw[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
 #pragma unroll
         for (int e = 0; e < 8; ++e) gd[buf][ks][e] = lds_at_u2(fw[e] + MOFF);
       }
     };
-    load_fq(0, 0);
-    if constexpr (GPF) {
-      gather(0);
-      if (NS > 1) load_fq(1, 1);
-    }
+    load_fq(0);
+    if constexpr (GPF) gather(0);
     static_for<0, NS>([&](auto sc) {
       constexpr int s = decltype(sc)::value;
       if constexpr (GPF) {
-        if constexpr (s + 1 < NS) gather((s + 1) & 1);
-        if constexpr (s + 2 < NS) load_fq(s & 1, s + 2);
-      } else if constexpr (s + 1 < NS) {
-        load_fq((s + 1) & 1, s + 1);
+        if constexpr (s + 1 < NS) {
+          load_fq(s + 1);
+          gather((s + 1) & 1);
+        }
       }
       // ---- row pass of step s
       f32x4 racc[NPL];
@@ -489,7 +488,8 @@ __device__ __forceinline__ void wave_tile_wide(const JobDesc& job, int X0, int Y
           racc[3] = PT::mma(a, brow[ks], racc[3]);
         } else {
           // harmonic 0: the (f - c0) cos half of the harmonic-0 entry (cos = 1)
-          const uint4 a0 = fq_pf[s & 1][ks][0], a1 = fq_pf[s & 1][ks][1];
+          if (ks == 0) load_fq(s);
+          const uint4 a0 = fq_pf[ks][0], a1 = fq_pf[ks][1];
           const uint32_t fw[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
           uint32_t pv[4];
 #pragma unroll
