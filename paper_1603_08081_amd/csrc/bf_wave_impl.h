@@ -40,14 +40,6 @@ constexpr int kWaveNW = BF_WAVE_NW;              // waves per workgroup
 constexpr int kWaveThreads = 64 * kWaveNW;
 constexpr int kWaveCols = 16 * kWaveNW;          // output columns per tile
 
-// read the next row-pass step's gray-level offsets one step ahead
-#ifndef BF_WAVE_PREFETCH
-#define BF_WAVE_PREFETCH 1
-#endif
-// also issue the next step's table gathers before this step's permutes
-#ifndef BF_WAVE_GATHER_AHEAD
-#define BF_WAVE_GATHER_AHEAD 1
-#endif
 // optional register budget of the wave kernels (waves per SIMD)
 #ifdef BF_WAVE_MIN_WAVES
 #define BF_WAVE_OCC __attribute__((amdgpu_waves_per_eu(BF_WAVE_MIN_WAVES)))
@@ -163,13 +155,6 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
   double wsum = 0.0;
   for (int t = -W; t <= W; ++t) wsum += (double)wq(t);
   const float q0 = (float)(job.d[0] * wsum * wsum);
-  // table byte offsets of this lane's output pixels, two per register
-  uint32_t fo[NJ][2];
-  for (int j = 0; j < NJ; ++j) {
-    const uint2 q = *reinterpret_cast<const uint2*>(&ftile[W + 16 * j + n16][Wal + 16 * wave + 4 * g]);
-    fo[j][0] = q.x;
-    fo[j][1] = q.y;
-  }
   float P[NJ][4], Q[NJ][4];
   for (int j = 0; j < NJ; ++j)
     for (int i = 0; i < 4; ++i) P[j][i] = Q[j][i] = 0.f;
@@ -203,23 +188,22 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
     auto run = [&](auto nplc) {
       constexpr int NPL = decltype(nplc)::value;  // 1 for k = 0 (plane f - c0 only), else 4
       typename PT::V4 ring[NT][NPL];
-      // gray-level offsets of the row-pass operands, read one step ahead so
-      // that the LDS latency of the next step hides behind this one
-      constexpr bool PF = BF_WAVE_PREFETCH;
-      // with GPF the table gathers of step s + 1 are also issued before the
-      // permutes and MFMAs of step s (two buffers of gathered entries)
-      constexpr bool GPF = PF && BF_WAVE_GATHER_AHEAD && NPL == 4;
-      uint4 fq_pf[2][PF ? KS : 1];
+      // gray-level offsets of one step (read one step ahead) and, for the
+      // four-plane harmonics, the gathered entries of two steps: the table
+      // gathers of step s + 1 are issued before the permutes and MFMAs of
+      // step s, so that their LDS latency hides behind them
+      constexpr bool GPF = NPL == 4;
+      uint4 fq_pf[KS];
       uint2 gd[GPF ? 2 : 1][GPF ? KS : 1][8];
-      auto load_fq = [&](int buf, int step) {
+      auto load_fq = [&](int step) {
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
-          fq_pf[buf][ks] = *reinterpret_cast<const uint4*>(&ftile[16 * step + n16][16 * wave + 32 * ks + 8 * g]);
+          fq_pf[ks] = *reinterpret_cast<const uint4*>(&ftile[16 * step + n16][16 * wave + 32 * ks + 8 * g]);
       };
       auto gather = [&](int buf) {
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-          const uint4 fq = fq_pf[buf][ks];
+          const uint4 fq = fq_pf[ks];
           const uint32_t fw[4] = {fq.x, fq.y, fq.z, fq.w};
 #pragma unroll
           for (int h = 0; h < 4; ++h) {
@@ -228,18 +212,15 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
           }
         }
       };
-      if constexpr (PF) load_fq(0, 0);
       if constexpr (GPF) {
+        load_fq(0);
         gather(0);
-        if (NS > 1) load_fq(1, 1);
       }
       static_for<0, NS>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
-        if constexpr (GPF) {
-          if constexpr (s + 1 < NS) gather((s + 1) & 1);
-          if constexpr (s + 2 < NS) load_fq(s & 1, s + 2);
-        } else if constexpr (PF && s + 1 < NS) {
-          load_fq((s + 1) & 1, s + 1);
+        if constexpr (GPF && s + 1 < NS) {
+          load_fq(s + 1);
+          gather((s + 1) & 1);
         }
         // ---- row pass of step s: operands gathered straight into registers
         f32x4 racc[NPL];
@@ -252,18 +233,7 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
             uint32_t pc[4], ps[4], pfc[4], pfs[4];
 #pragma unroll
             for (int h = 0; h < 4; ++h) {  // pixels 2h, 2h + 1
-              uint2 ta, tb;
-              if constexpr (GPF) {
-                ta = gd[s & 1][ks][2 * h];
-                tb = gd[s & 1][ks][2 * h + 1];
-              } else {
-                uint4 fq;
-                if constexpr (PF) fq = fq_pf[s & 1][ks];
-                else fq = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
-                const uint32_t fw[4] = {fq.x, fq.y, fq.z, fq.w};  // table offsets of pixels 2h, 2h + 1
-                ta = *reinterpret_cast<const uint2*>(tm + (fw[h] & 0xffffu));
-                tb = *reinterpret_cast<const uint2*>(tm + (fw[h] >> 16));
-              }
+              const uint2 ta = gd[s & 1][ks][2 * h], tb = gd[s & 1][ks][2 * h + 1];
               pc[h] = lo_halves(ta.x, tb.x);
               ps[h] = hi_halves(ta.x, tb.x);
               pfc[h] = lo_halves(ta.y, tb.y);
@@ -279,9 +249,7 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
             racc[3] = PT::mma(a, brow[ks], racc[3]);
           } else {
             // harmonic 0: the single plane f - c0
-            uint4 fq;
-            if constexpr (PF) fq = fq_pf[s & 1][ks];
-            else fq = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
+            const uint4 fq = *reinterpret_cast<const uint4*>(&ftile[rr][cc]);
             const uint32_t fw[4] = {fq.x, fq.y, fq.z, fq.w};
             uint32_t pv[4];
 #pragma unroll
@@ -319,7 +287,10 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
             for (int i = 0; i < 4; ++i) fb[pi][i] = acc[i];
           }
           if constexpr (NPL == 4) {
-            const uint32_t off[4] = {fo[j][0] & 0xffffu, fo[j][0] >> 16, fo[j][1] & 0xffffu, fo[j][1] >> 16};
+            // table offsets of this lane's output pixels (row 16 j + n16,
+            // columns 4 g .. 4 g + 3 of the strip), read from the tile
+            const uint2 fo = *reinterpret_cast<const uint2*>(&ftile[W + 16 * j + n16][Wal + 16 * wave + 4 * g]);
+            const uint32_t off[4] = {fo.x & 0xffffu, fo.x >> 16, fo.y & 0xffffu, fo.y >> 16};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const float2 t = *reinterpret_cast<const float2*>(td + off[i]);
