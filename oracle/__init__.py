@@ -13,6 +13,8 @@ Parts:
   filters.shiftable_alg1    Algorithm 1 in complex FP64 (numpy)
   filters.brute_direct      eq. (1) in pure Python, tiny images
   dynamic_range.local_dynamic_range   the dynamic range T of Sec. 3 measured on an image
+  recursive.fourier_recursive  eq. (9) with Deriche's recursive Gaussian as the
+                               spatial smoothing (Sec. 2), FP64 numpy
 """
 from .fit import (  # noqa: F401
     FitResult, accuracy_bound, back_substitute, fit_kernel, progressive_fit, sample_kernel, series,
