@@ -288,6 +288,32 @@ size_t bf_dynamic_range_workspace_bytes(int height, int width);
 int bf_dynamic_range(const float* src, int height, int width, int src_pitch, int W, int* T_out,
                      void* workspace, size_t ws_bytes, void* hip_stream);
 
+/*
+ * bf_filter_recursive -- eq. (9) for one image with every spatial
+ * convolution of Algorithm 1 done by Deriche's recursive Gaussian, the
+ * constant-time smoothing Sec. 2 cites (after eq. (5)): exp(-x^2 / 2 sigma_s^2)
+ * fitted by two damped cosine/sine pairs, run as a causal plus an
+ * anti-causal fourth-order recursion along rows, then along columns, over a
+ * half-sample symmetric extension of about 21 sigma_s + 8 samples, with unit
+ * sum.  Its run time does not grow with sigma_s beyond that extension; its
+ * result differs from bf_filter's truncated Gaussian of eq. (2) by the
+ * difference of the two spatial kernels (a variant, not the same filter).
+ *   job         as for bf_filter, except: spatial must be BF_SPATIAL_GAUSSIAN,
+ *               0 < sigma_s <= 1024, W is not used, flags and f_max only as
+ *               validated there (phases are taken per pixel in float64)
+ *   workspace   device memory of at least bf_recursive_workspace_bytes(height,
+ *               width) bytes (48 per pixel: the row-smoothed planes, the
+ *               causal column part, float64 numerator and denominator),
+ *               256-byte aligned, owned by the caller, not overlapping src or
+ *               dst; in use until the stream has passed the launches
+ *   hip_stream  stream to enqueue on: two launches per harmonic, asynchronous
+ * Returns BF_OK, BF_FIT_NOT_CONVERGED, BF_E_INVALID, BF_E_UNSUPPORTED,
+ * BF_E_WORKSPACE or BF_E_DEVICE; nothing is enqueued on a negative status.
+ * bf_recursive_workspace_bytes returns (size_t)-1 for sizes below 1.
+ */
+size_t bf_recursive_workspace_bytes(int height, int width);
+int bf_filter_recursive(const bf_job* job, void* workspace, size_t ws_bytes, void* hip_stream);
+
 /* Thread-local text describing the last non-OK status of this thread. */
 const char* bf_last_error(void);
 

@@ -35,6 +35,7 @@ def _units():
     for s in HOST_SRCS:
         units.append((os.path.join(CSRC, s), os.path.join(BUILD, s.replace(".cpp", ".o")), []))
     units.append((os.path.join(CSRC, "bf_range.hip"), os.path.join(BUILD, "bf_range.o"), []))
+    units.append((os.path.join(CSRC, "bf_recursive.hip"), os.path.join(BUILD, "bf_recursive.o"), []))
     for p in PRECS:
         for nt in NTS:
             units.append((os.path.join(CSRC, "bf_fused_inst.hip"),

@@ -1,0 +1,312 @@
+// Eq. (9) with the spatial convolutions of Algorithm 1 done by Deriche's
+// recursive Gaussian, the constant-time smoothing Sec. 2 cites: per harmonic
+// k = 0..K, two launches.
+//   1. rows:    one lane per image row modulates f into the four planes
+//               f cos, f sin, cos, sin of k w f (w = pi / T) and runs the
+//               causal and anti-causal fourth-order recursions over the row
+//               (half-sample symmetric extension), writing the row-smoothed
+//               planes;
+//   2. columns: one lane per image column runs the same recursions down the
+//               row-smoothed planes, demodulates with d_k (cos S(f cos) +
+//               sin S(f sin) into the numerator, cos S(cos) + sin S(sin) into
+//               the denominator, float64 accumulators) and, for the last
+//               harmonic, writes numerator / denominator.
+// The recursions' state and the phases are float64; the planes between the
+// passes are float32.  The recursion coefficients come from the four poles of
+// Deriche's two damped cosine/sine pairs (his published fit of exp(-x^2/2)):
+// the causal half of the kernel is a sum of four one-pole terms, whose common
+// denominator and numerator give the recursion, and the anti-causal half
+// (n >= 1, run backwards) has numerator N(z) - g(0) D(z).  Scaled to unit sum.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+
+#include "bf_internal.h"
+
+namespace bf {
+namespace {
+
+constexpr int kLineThreads = 64;     // one wavefront of lines per workgroup
+constexpr double kMaxSigmaRec = 1024.0;
+
+struct RecCoef {
+  double nc[4];   // causal numerator, x(i) .. x(i - 3)
+  double na[5];   // anti-causal numerator, x(i + 1) .. x(i + 4) in [1..4]
+  double dd[5];   // denominator 1, d1..d4 (same for both directions)
+  int margin;     // samples of symmetric extension before and after the line
+};
+
+struct RecArgs {
+  const float* src;
+  float* dst;
+  int height, width, src_pitch, dst_pitch;
+  int T;
+  int k;
+  int last;        // 1 on the last harmonic: write the quotient
+  double dk;       // d_k
+  RecCoef c;
+  float* rows;     // 4 planes [4][height][width], row-smoothed
+  float* causal;   // 4 planes [4][height][width], causal part of the column pass
+  double* P;       // [height][width]
+  double* Q;       // [height][width]
+};
+
+// Deriche's fit of exp(-x^2 / 2), x >= 0: two damped pairs
+// (a cos(w x) + a' sin(w x)) e^{-b x}
+constexpr double kFitCos[2] = {1.680, -0.6803};
+constexpr double kFitSin[2] = {3.735, -0.2598};
+constexpr double kFitDecay[2] = {1.783, 1.723};
+constexpr double kFitFreq[2] = {0.6318, 1.997};
+
+RecCoef recursion_coefficients(double sigma) {
+  using cd = std::complex<double>;
+  cd poles[4], res[4];
+  for (int p = 0; p < 2; ++p) {
+    const cd z = std::polar(std::exp(-kFitDecay[p] / sigma), kFitFreq[p] / sigma);
+    const cd alpha(kFitCos[p], -kFitSin[p]);
+    poles[2 * p] = z;
+    poles[2 * p + 1] = std::conj(z);
+    res[2 * p] = 0.5 * alpha;
+    res[2 * p + 1] = 0.5 * std::conj(alpha);
+  }
+  // D(u) = prod (1 - p u), u = z^-1, lowest power first
+  cd D[5] = {1.0, 0.0, 0.0, 0.0, 0.0};
+  for (int j = 0; j < 4; ++j)
+    for (int m = j + 1; m >= 1; --m) D[m] -= poles[j] * D[m - 1];
+  // N(u) = sum_j r_j prod_{m != j} (1 - p_m u)
+  cd N[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int j = 0; j < 4; ++j) {
+    cd t[4] = {1.0, 0.0, 0.0, 0.0};
+    int deg = 0;
+    for (int m = 0; m < 4; ++m) {
+      if (m == j) continue;
+      ++deg;
+      for (int q = deg; q >= 1; --q) t[q] -= poles[m] * t[q - 1];
+    }
+    for (int q = 0; q < 4; ++q) N[q] += res[j] * t[q];
+  }
+  RecCoef c{};
+  double sum_n = 0.0, sum_a = 0.0, sum_d = 0.0;
+  const double g0 = N[0].real();
+  for (int q = 0; q < 5; ++q) c.dd[q] = D[q].real();
+  for (int q = 0; q < 4; ++q) c.nc[q] = N[q].real();
+  c.na[0] = 0.0;
+  for (int q = 1; q < 4; ++q) c.na[q] = c.nc[q] - g0 * c.dd[q];
+  c.na[4] = -g0 * c.dd[4];
+  for (int q = 0; q < 4; ++q) sum_n += c.nc[q];
+  for (int q = 1; q < 5; ++q) sum_a += c.na[q];
+  for (int q = 0; q < 5; ++q) sum_d += c.dd[q];
+  const double total = (sum_n + sum_a) / sum_d;
+  for (int q = 0; q < 4; ++q) c.nc[q] /= total;
+  for (int q = 1; q < 5; ++q) c.na[q] /= total;
+  // the slowest decay is e^{-b n / sigma}: beyond this the kernel is < 1e-16 of its peak
+  c.margin = static_cast<int>(std::ceil(sigma * 16.0 * std::log(10.0) / kFitDecay[1])) + 8;
+  return c;
+}
+
+// half-sample symmetric extension of a line of length L, any index
+__device__ __forceinline__ int fold(int i, int L) {
+  const int P = 2 * L;
+  int j = i % P;
+  if (j < 0) j += P;
+  return j < L ? j : P - 1 - j;
+}
+
+// cos and sin of k pi f / T, the product reduced mod 2T first
+__device__ __forceinline__ void phase(float f, int k, int T, double* c, double* s) {
+  double a = static_cast<double>(k) * static_cast<double>(f);
+  a = fmod(a, 2.0 * T);
+  sincospi(a / T, s, c);
+}
+
+__global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a) {
+  const int y = blockIdx.x * kLineThreads + threadIdx.x;
+  if (y >= a.height) return;
+  const int L = a.width, M = a.c.margin;
+  const size_t plane = (size_t)a.height * a.width;
+  const float* frow = a.src + (size_t)y * a.src_pitch;
+  float* out = a.rows + (size_t)y * a.width;
+  double xh[4][4] = {};  // x(i), x(i-1), x(i-2), x(i-3) per plane
+  double yh[4][4] = {};  // y(i-1) .. y(i-4)
+  for (int i = -M; i < L; ++i) {
+    const float f = frow[fold(i, L)];
+    double c, s;
+    phase(f, a.k, a.T, &c, &s);
+    const double x[4] = {f * c, f * s, c, s};
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      xh[p][3] = xh[p][2];
+      xh[p][2] = xh[p][1];
+      xh[p][1] = xh[p][0];
+      xh[p][0] = x[p];
+      const double v = a.c.nc[0] * xh[p][0] + a.c.nc[1] * xh[p][1] + a.c.nc[2] * xh[p][2] + a.c.nc[3] * xh[p][3] -
+                       a.c.dd[1] * yh[p][0] - a.c.dd[2] * yh[p][1] - a.c.dd[3] * yh[p][2] - a.c.dd[4] * yh[p][3];
+      yh[p][3] = yh[p][2];
+      yh[p][2] = yh[p][1];
+      yh[p][1] = yh[p][0];
+      yh[p][0] = v;
+      if (i >= 0) out[p * plane + i] = static_cast<float>(v);
+    }
+  }
+  double xa[4][4] = {};  // x(i+1) .. x(i+4)
+  double ya[4][4] = {};  // y(i+1) .. y(i+4)
+  for (int i = L - 1 + M; i >= 0; --i) {
+    const float f = frow[fold(i, L)];
+    double c, s;
+    phase(f, a.k, a.T, &c, &s);
+    const double x[4] = {f * c, f * s, c, s};
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const double v = a.c.na[1] * xa[p][0] + a.c.na[2] * xa[p][1] + a.c.na[3] * xa[p][2] + a.c.na[4] * xa[p][3] -
+                       a.c.dd[1] * ya[p][0] - a.c.dd[2] * ya[p][1] - a.c.dd[3] * ya[p][2] - a.c.dd[4] * ya[p][3];
+      ya[p][3] = ya[p][2];
+      ya[p][2] = ya[p][1];
+      ya[p][1] = ya[p][0];
+      ya[p][0] = v;
+      xa[p][3] = xa[p][2];
+      xa[p][2] = xa[p][1];
+      xa[p][1] = xa[p][0];
+      xa[p][0] = x[p];
+      if (i < L) out[p * plane + i] = static_cast<float>(out[p * plane + i] + v);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kLineThreads) rec_cols_kernel(const RecArgs a) {
+  const int x0 = blockIdx.x * kLineThreads + threadIdx.x;
+  if (x0 >= a.width) return;
+  const int L = a.height, M = a.c.margin, Wd = a.width;
+  const size_t plane = (size_t)a.height * a.width;
+  const float* in = a.rows + x0;
+  float* cz = a.causal + x0;
+  double xh[4][4] = {};
+  double yh[4][4] = {};
+  for (int i = -M; i < L; ++i) {
+    const size_t r = (size_t)fold(i, L) * Wd;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      xh[p][3] = xh[p][2];
+      xh[p][2] = xh[p][1];
+      xh[p][1] = xh[p][0];
+      xh[p][0] = in[p * plane + r];
+      const double v = a.c.nc[0] * xh[p][0] + a.c.nc[1] * xh[p][1] + a.c.nc[2] * xh[p][2] + a.c.nc[3] * xh[p][3] -
+                       a.c.dd[1] * yh[p][0] - a.c.dd[2] * yh[p][1] - a.c.dd[3] * yh[p][2] - a.c.dd[4] * yh[p][3];
+      yh[p][3] = yh[p][2];
+      yh[p][2] = yh[p][1];
+      yh[p][1] = yh[p][0];
+      yh[p][0] = v;
+      if (i >= 0) cz[p * plane + r] = static_cast<float>(v);
+    }
+  }
+  double xa[4][4] = {};
+  double ya[4][4] = {};
+  for (int i = L - 1 + M; i >= 0; --i) {
+    const size_t r = (size_t)fold(i, L) * Wd;
+    double S[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const double v = a.c.na[1] * xa[p][0] + a.c.na[2] * xa[p][1] + a.c.na[3] * xa[p][2] + a.c.na[4] * xa[p][3] -
+                       a.c.dd[1] * ya[p][0] - a.c.dd[2] * ya[p][1] - a.c.dd[3] * ya[p][2] - a.c.dd[4] * ya[p][3];
+      ya[p][3] = ya[p][2];
+      ya[p][2] = ya[p][1];
+      ya[p][1] = ya[p][0];
+      ya[p][0] = v;
+      xa[p][3] = xa[p][2];
+      xa[p][2] = xa[p][1];
+      xa[p][1] = xa[p][0];
+      xa[p][0] = in[p * plane + r];
+      S[p] = v;
+    }
+    if (i < L) {
+      for (int p = 0; p < 4; ++p) S[p] += cz[p * plane + r];
+      const float f = a.src[(size_t)i * a.src_pitch + x0];
+      double c, s;
+      phase(f, a.k, a.T, &c, &s);
+      const size_t o = (size_t)i * Wd + x0;
+      double pn = a.dk * (c * S[0] + s * S[1]);
+      double qn = a.dk * (c * S[2] + s * S[3]);
+      if (a.k > 0) {
+        pn += a.P[o];
+        qn += a.Q[o];
+      }
+      if (a.last) {
+        a.dst[(size_t)i * a.dst_pitch + x0] = static_cast<float>(pn / qn);
+      } else {
+        a.P[o] = pn;
+        a.Q[o] = qn;
+      }
+    }
+  }
+}
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t rec_ws_bytes(int height, int width) {
+  const size_t n = (size_t)height * width;
+  return 2 * align256(4 * n * sizeof(float)) + 2 * align256(n * sizeof(double));
+}
+
+}  // namespace
+}  // namespace bf
+
+using namespace bf;
+
+extern "C" size_t bf_recursive_workspace_bytes(int height, int width) {
+  if (height < 1 || width < 1) {
+    set_error("height and width must be >= 1");
+    return (size_t)-1;
+  }
+  return rec_ws_bytes(height, width);
+}
+
+extern "C" int bf_filter_recursive(const bf_job* job, void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (!job) return fail(BF_E_INVALID, "job is NULL");
+  if (job->spatial != BF_SPATIAL_GAUSSIAN)
+    return fail(BF_E_INVALID, "the recursive path smooths with a Gaussian: spatial must be BF_SPATIAL_GAUSSIAN");
+  if (!(job->sigma_s > 0.0) || !std::isfinite(job->sigma_s))
+    return fail(BF_E_INVALID, "sigma_s must be finite and > 0");
+  if (job->sigma_s > kMaxSigmaRec) return fail(BF_E_UNSUPPORTED, "sigma_s exceeds 1024");
+  // validation and fit shared with bf_filter; the window does not apply here
+  bf_job j = *job;
+  j.W = 0;
+  Resolved r;
+  const int rc = resolve_job(&j, &r);
+  if (rc < 0) return rc;
+  if (!workspace) return fail(BF_E_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < rec_ws_bytes(job->height, job->width))
+    return fail(BF_E_WORKSPACE, "workspace smaller than bf_recursive_workspace_bytes()");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(BF_E_WORKSPACE, "workspace must be 256-byte aligned");
+  const size_t n = (size_t)job->height * job->width;
+  unsigned char* w = static_cast<unsigned char*>(workspace);
+  RecArgs a{};
+  a.src = job->src;
+  a.dst = job->dst;
+  a.height = job->height;
+  a.width = job->width;
+  a.src_pitch = job->src_pitch;
+  a.dst_pitch = job->dst_pitch;
+  a.T = job->T;
+  a.c = recursion_coefficients(job->sigma_s);
+  a.rows = reinterpret_cast<float*>(w);
+  a.causal = reinterpret_cast<float*>(w + align256(4 * n * sizeof(float)));
+  a.P = reinterpret_cast<double*>(w + 2 * align256(4 * n * sizeof(float)));
+  a.Q = reinterpret_cast<double*>(w + 2 * align256(4 * n * sizeof(float)) + align256(n * sizeof(double)));
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  const int K = r.desc.K;
+  const dim3 grows((job->height + kLineThreads - 1) / kLineThreads);
+  const dim3 gcols((job->width + kLineThreads - 1) / kLineThreads);
+  for (int k = 0; k <= K; ++k) {
+    a.k = k;
+    a.dk = r.desc.d[k];
+    a.last = k == K ? 1 : 0;
+    hipLaunchKernelGGL(rec_rows_kernel, grows, dim3(kLineThreads), 0, stream, a);
+    hipLaunchKernelGGL(rec_cols_kernel, gcols, dim3(kLineThreads), 0, stream, a);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(BF_E_DEVICE, std::string("recursive-filter launch failed: ") + hipGetErrorString(e));
+  return r.status;
+}

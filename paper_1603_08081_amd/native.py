@@ -109,6 +109,10 @@ def _load():
     lib.bf_dynamic_range_workspace_bytes.restype = Z
     lib.bf_dynamic_range.argtypes = [P, I, I, I, I, P, P, Z, P]
     lib.bf_dynamic_range.restype = I
+    lib.bf_recursive_workspace_bytes.argtypes = [I, I]
+    lib.bf_recursive_workspace_bytes.restype = Z
+    lib.bf_filter_recursive.argtypes = [jp, P, Z, P]
+    lib.bf_filter_recursive.restype = I
     lib.bf_last_error.argtypes = []
     lib.bf_last_error.restype = ctypes.c_char_p
     hip = sorted(p for p in _hip_runtimes() if "libamdhip64" in p)
@@ -294,6 +298,20 @@ def bf_dynamic_range(src, W: int, T_out, workspace, ws_bytes: int, stream=None, 
     pitch = int(src_pitch if src_pitch is not None else _pitch(src, w))
     return _check(lib.bf_dynamic_range(_ptr(src), int(h), int(w), pitch, int(W), _ptr(T_out), _ptr(workspace),
                                        int(ws_bytes), _stream_handle(stream)))
+
+
+def bf_recursive_workspace_bytes(height: int, width: int) -> int:
+    n = lib.bf_recursive_workspace_bytes(int(height), int(width))
+    if n == ctypes.c_size_t(-1).value:
+        raise BfError(BF_E_INVALID, "height and width must be >= 1")
+    return int(n)
+
+
+def bf_filter_recursive(job: Job, workspace, ws_bytes: int, stream=None) -> int:
+    """bf_filter_recursive: eq. (9) with Deriche's recursive Gaussian as the
+    spatial smoothing (asynchronous)."""
+    return _check(lib.bf_filter_recursive(ctypes.byref(job.struct), _ptr(workspace), int(ws_bytes),
+                                          _stream_handle(stream)))
 
 
 def bf_tune_save(path: str) -> int:

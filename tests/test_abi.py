@@ -279,3 +279,38 @@ def test_batched_rejects_outputs_that_overlap_other_jobs():
     bad = [_job(dst=FAKE_DST, **a), _job(src=FAKE_DST + 4 * 64 * 63, dst=FAKE_DST + (1 << 22), **a)]
     with pytest.raises(native.BfError):
         native.bf_filter_batched(bad, "fp32", stream=0)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(src=None), native.BF_E_INVALID),
+    (dict(height=0), native.BF_E_INVALID),
+    (dict(src_pitch=10), native.BF_E_INVALID),
+    (dict(spatial="box", W=3), native.BF_E_INVALID),
+    (dict(sigma_s=0.0), native.BF_E_INVALID),
+    (dict(sigma_s=2000.0), native.BF_E_UNSUPPORTED),
+    (dict(T=0), native.BF_E_INVALID),
+    (dict(sigma_r=-1.0), native.BF_E_INVALID),
+    (dict(d=np.ones(300)), native.BF_E_UNSUPPORTED),
+    (dict(dst=FAKE_SRC + 4 * 100), native.BF_E_INVALID),
+])
+def test_recursive_filter_rejects_bad_jobs_before_device_work(kw, code):
+    j = _job(**kw)
+    ws = native.bf_recursive_workspace_bytes(64, 64)
+    with pytest.raises(native.BfError) as ei:
+        native.bf_filter_recursive(j, 0x30000000, ws, stream=0)
+    assert ei.value.code == code
+    assert native.bf_last_error()
+
+
+def test_recursive_filter_workspace_checks():
+    # 48 bytes per pixel, each of the four regions 256-byte aligned
+    assert native.bf_recursive_workspace_bytes(64, 64) == 48 * 64 * 64
+    assert native.bf_recursive_workspace_bytes(3, 5) == 4 * 256
+    with pytest.raises(native.BfError):
+        native.bf_recursive_workspace_bytes(0, 5)
+    j = _job(W=0)
+    ws = native.bf_recursive_workspace_bytes(64, 64)
+    for ptr, n in ((None, ws), (0x30000000, ws - 1), (0x30000004, ws)):
+        with pytest.raises(native.BfError) as ei:
+            native.bf_filter_recursive(j, ptr, n, stream=0)
+        assert ei.value.code == native.BF_E_WORKSPACE

@@ -1,0 +1,85 @@
+"""GPU parity of bf_filter_recursive (eq. (9) with Deriche's recursive
+Gaussian as the spatial smoothing, Sec. 2) against the FP64 oracle
+``oracle.recursive.fourier_recursive``, element by element."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import recursive as R
+from synth import polygon_image
+
+pytestmark = pytest.mark.gpu
+
+# float32 planes between the passes, float64 recursions and accumulators
+TOL = 1e-3
+
+
+def _run(f, **kw):
+    import torch
+
+    import paper_1603_08081_amd as bfm
+    x = torch.from_numpy(np.ascontiguousarray(f, dtype=np.float32)).cuda()
+    out, st = bfm.filter_recursive(x, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), st
+
+
+@pytest.mark.parametrize("H,Wd,sigma_s,sigma_r,seed", [
+    (70, 150, 2.0, 20.0, 1),    # several 64-line workgroups with ragged tails, both directions
+    (33, 47, 5.5, 30.0, 2),     # extension longer than the image: repeated folding
+    (1, 9, 1.0, 15.0, 3),       # a single row
+    (64, 1, 1.5, 25.0, 4),      # a single column
+])
+def test_matches_the_oracle_on_integer_images(H, Wd, sigma_s, sigma_r, seed):
+    f = polygon_image(H, Wd, seed).astype(np.float32)
+    fit = oracle.fit_kernel("gaussian", sigma_r, 255, 1e-3)
+    print("recursive parity", H, Wd, sigma_s, sigma_r, seed, "K", fit.K, flush=True)
+    out, st = _run(f, sigma_s=sigma_s, T=255, d=fit.d, integer_input=True)
+    want = R.fourier_recursive(f, sigma_s, fit.d, 255)
+    assert st == 0
+    assert np.abs(out - want).max() <= TOL
+
+
+def test_fit_on_the_device_side_and_non_integer_image():
+    rng = np.random.default_rng(7)
+    f = (polygon_image(40, 72, 5) + rng.uniform(-0.5, 0.5, (40, 72))).clip(0, 255).astype(np.float32)
+    out, st = _run(f, sigma_s=3.0, range_kind="exponential", sigma_r=20.0, T=255, eps=1e-2, K_max=40)
+    fit = oracle.fit_kernel("exponential", 20.0, 255, 1e-2, 40)
+    want = R.fourier_recursive(f, 3.0, fit.d, 255)
+    assert st in (0, 1)
+    assert np.abs(out - want).max() <= TOL
+
+
+def test_zero_order_is_the_plain_recursive_smoothing():
+    f = polygon_image(50, 66, 9).astype(np.float32)
+    out, _ = _run(f, sigma_s=2.5, T=255, d=np.array([0.8]))
+    assert np.abs(out - R.convolve_smooth(f.astype(np.float64), 2.5)).max() <= TOL
+
+
+def test_pitched_views_and_repeat_calls_give_the_same_bits():
+    import torch
+
+    import paper_1603_08081_amd as bfm
+    f = polygon_image(45, 80, 11).astype(np.float32)
+    fit = oracle.fit_kernel("gaussian", 25.0, 255, 1e-3)
+    base = torch.zeros((45, 100), dtype=torch.float32, device="cuda")
+    base[:, :80] = torch.from_numpy(f).cuda()
+    outbuf = torch.full((45, 120), -3.0, device="cuda")
+    view_out = outbuf[:, 20:100]
+    bfm.filter_recursive(base[:, :80], sigma_s=2.0, T=255, d=fit.d, out=view_out)
+    torch.cuda.synchronize()
+    o1 = outbuf.cpu().numpy()
+    assert (o1[:, :20] == -3.0).all() and (o1[:, 100:] == -3.0).all()
+    assert np.abs(o1[:, 20:100] - R.fourier_recursive(f, 2.0, fit.d, 255)).max() <= TOL
+    bfm.filter_recursive(base[:, :80], sigma_s=2.0, T=255, d=fit.d, out=view_out)
+    torch.cuda.synchronize()
+    assert np.array_equal(outbuf.cpu().numpy(), o1)
+
+
+def test_close_to_the_truncated_gaussian_path_at_moderate_sigma():
+    # the variant differs from eq. (2)'s truncated kernel by the kernels' difference only
+    f = polygon_image(96, 128, 13).astype(np.float32)
+    fit = oracle.fit_kernel("gaussian", 30.0, 255, 1e-3)
+    out, _ = _run(f, sigma_s=3.0, T=255, d=fit.d, integer_input=True)
+    trunc = oracle.fourier(f, "gaussian", 3.0, 12, fit.d, 255)
+    assert np.abs(out - trunc).max() < 0.1
