@@ -60,15 +60,20 @@ def issued_flops_per_px(K, W, tile_rows):
     return per_plane * (4 * K + 1)
 
 
+# standalone HIP units that share no code with the filter kernels measured here
+_OTHER_UNITS = ("bf_range.hip", "bf_recursive.hip")
+
+
 def kernel_sources_digest():
-    """sha256 over the sources the kernels are compiled from (the HIP files
-    and the headers they include; byte counters taken on other sources no
-    longer describe the kernel).  Host-only .cpp files are not part of it."""
+    """sha256 over the sources the filter kernels are compiled from (their HIP
+    file and the headers it includes; byte counters taken on other sources no
+    longer describe the kernel).  Host-only .cpp files and the standalone
+    units of other operations are not part of it."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1603_08081_amd", "csrc")
     h = hashlib.sha256()
     for fn in sorted(os.listdir(csrc)):
-        if fn.endswith((".h", ".hip")):
+        if fn.endswith((".h", ".hip")) and fn not in _OTHER_UNITS:
             h.update(fn.encode())
             with open(os.path.join(csrc, fn), "rb") as fh:
                 h.update(fh.read())
@@ -172,6 +177,72 @@ def run_sweep(args):
         print(json.dumps(line), flush=True)
 
 
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+
+
+def recursive_flops_per_px(K):
+    """Recursions of the recursive-Gaussian path: per harmonic, four planes,
+    two axes, a causal and an anti-causal fourth-order recursion of 8
+    multiply-adds each (float64)."""
+    return (K + 1) * 4 * 2 * 2 * 8 * 2
+
+
+def recursive_bytes_per_px(K):
+    """Bytes per pixel the recursive-Gaussian path moves to and from memory
+    (before caches), per harmonic: the row pass reads f in both directions and
+    writes, re-reads and rewrites four float32 planes (56); the column pass
+    reads them in both directions, writes and re-reads its causal parts,
+    reads f and writes two float32 shares (76); the final sum reads the
+    shares (8).  Plus the output."""
+    return (K + 1) * (56 + 76 + 8) + 4
+
+
+def run_recursive(args):
+    import torch
+
+    import paper_1603_08081_amd as bfm  # noqa: F401
+    from paper_1603_08081_amd import native
+    from synth import WORKLOADS, workload_images
+    wl = WORKLOADS[args.workload]
+    img = workload_images(args.workload, limit=1)[0]
+    H, Wd = img.shape
+    src = torch.from_numpy(np.ascontiguousarray(img, dtype=np.float32)).cuda()
+    out = torch.empty_like(src)
+    job = native.Job(src, out, spatial="gaussian", sigma_s=wl["sigma_s"], W=0, range_kind=wl["range_kind"],
+                     sigma_r=wl["sigma_r"], T=wl["T"], eps=wl["eps"], K_max=wl["K_max"], integer_input=True)
+    K = len(native.bf_fit_coeffs(wl["range_kind"], wl["sigma_r"], wl["T"], wl["eps"], wl["K_max"])[1]) - 1
+    n = native.bf_recursive_workspace_bytes(job)
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        native.bf_filter_recursive(job, ws, n, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(args.steps):
+        e0.record(stream)
+        native.bf_filter_recursive(job, ws, n, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    px = H * Wd
+    fl = recursive_flops_per_px(K) * px / (ms * 1e-3) / 1e12
+    gbs = recursive_bytes_per_px(K) * px / (ms * 1e-3) / 1e9
+    line = {"metric": "recursive_filter_throughput", "value": round(px / (ms * 1e-3) / 1e6, 1),
+            "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "%s, first frame (%d x %d), recursive Gaussian sigma_s = %g, %s range "
+                                   "sigma_r = %g, K = %d" % (args.workload, H, Wd, wl["sigma_s"],
+                                                             wl["range_kind"], wl["sigma_r"], K)},
+            "roofline": {"bound": "alu", "achieved": round(fl, 2), "peak": PEAK_FP64_VECTOR_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(fl / PEAK_FP64_VECTOR_TFLOPS, 4), "traffic": None,
+                         "kernel": "rec_rows_kernel + rec_cols_kernel + rec_sum_kernel, 3 launches per step",
+                         "plane_bytes_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}}
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +269,9 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one plain elementwise copy (negation) of this many MiB of "
                          "float32, the known-size reference for HBM byte counters")
+    ap.add_argument("--recursive", action="store_true",
+                    help="instead of the headline line: bf_filter_recursive (Deriche's recursive "
+                         "Gaussian as the spatial smoothing) on one frame of the workload")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the headline line: the Tables 1-3 analogues (one JSON line per setting)")
     args = ap.parse_args()
@@ -210,6 +284,9 @@ def main():
 
     if args.sweep:
         run_sweep(args)
+        return
+    if args.recursive:
+        run_recursive(args)
         return
 
     import torch

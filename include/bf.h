@@ -301,17 +301,19 @@ int bf_dynamic_range(const float* src, int height, int width, int src_pitch, int
  *   job         as for bf_filter, except: spatial must be BF_SPATIAL_GAUSSIAN,
  *               0 < sigma_s <= 1024, W is not used, flags and f_max only as
  *               validated there (phases are taken per pixel in float64)
- *   workspace   device memory of at least bf_recursive_workspace_bytes(height,
- *               width) bytes (48 per pixel: the row-smoothed planes, the
- *               causal column part, float64 numerator and denominator),
- *               256-byte aligned, owned by the caller, not overlapping src or
- *               dst; in use until the stream has passed the launches
- *   hip_stream  stream to enqueue on: two launches per harmonic, asynchronous
+ *   workspace   device memory of at least bf_recursive_workspace_bytes(job)
+ *               bytes (40 (K + 1) per pixel: the row-smoothed planes and the
+ *               causal column parts of every harmonic, and each harmonic's
+ *               float32 shares of numerator and denominator), 256-byte
+ *               aligned, owned by the caller, not overlapping src or dst; in
+ *               use until the stream has passed the launches
+ *   hip_stream  stream to enqueue on: three launches, asynchronous
  * Returns BF_OK, BF_FIT_NOT_CONVERGED, BF_E_INVALID, BF_E_UNSUPPORTED,
  * BF_E_WORKSPACE or BF_E_DEVICE; nothing is enqueued on a negative status.
- * bf_recursive_workspace_bytes returns (size_t)-1 for sizes below 1.
+ * bf_recursive_workspace_bytes runs the fit of a job without d and returns
+ * (size_t)-1 for an invalid job (bf_last_error() says which).
  */
-size_t bf_recursive_workspace_bytes(int height, int width);
+size_t bf_recursive_workspace_bytes(const bf_job* job);
 int bf_filter_recursive(const bf_job* job, void* workspace, size_t ws_bytes, void* hip_stream);
 
 /* Thread-local text describing the last non-OK status of this thread. */

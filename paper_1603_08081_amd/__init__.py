@@ -45,7 +45,7 @@ def filter_recursive(img, *, sigma_s=3.0, range_kind="gaussian", sigma_r=30.0, T
     job = native.Job(img, out, spatial="gaussian", sigma_s=sigma_s, W=0, range_kind=range_kind,
                      sigma_r=sigma_r, T=T, eps=eps, K_max=K_max, d=d, phi_table=phi_table,
                      integer_input=integer_input, f_max=f_max)
-    n = native.bf_recursive_workspace_bytes(img.shape[0], img.shape[1])
+    n = native.bf_recursive_workspace_bytes(job)
     ws = torch.empty(n, dtype=torch.uint8, device=img.device)
     st = native.bf_filter_recursive(job, ws, n, stream=stream)
     out._bf_workspace = ws   # keeps the workspace alive until the caller drops the output

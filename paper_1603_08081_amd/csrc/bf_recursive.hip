@@ -1,18 +1,18 @@
 // Eq. (9) with the spatial convolutions of Algorithm 1 done by Deriche's
-// recursive Gaussian, the constant-time smoothing Sec. 2 cites: per harmonic
-// k = 0..K, two launches.
-//   1. rows:    one lane per image row modulates f into the four planes
+// recursive Gaussian, the constant-time smoothing Sec. 2 cites.  Three
+// launches, the harmonics k = 0..K side by side in the grid (blockIdx.y):
+//   1. rows:    one lane per (image row, k) modulates f into the four planes
 //               f cos, f sin, cos, sin of k w f (w = pi / T) and runs the
 //               causal and anti-causal fourth-order recursions over the row
 //               (half-sample symmetric extension), writing the row-smoothed
-//               planes;
-//   2. columns: one lane per image column runs the same recursions down the
-//               row-smoothed planes, demodulates with d_k (cos S(f cos) +
-//               sin S(f sin) into the numerator, cos S(cos) + sin S(sin) into
-//               the denominator, float64 accumulators) and, for the last
-//               harmonic, writes numerator / denominator.
-// The recursions' state and the phases are float64; the planes between the
-// passes are float32.  The recursion coefficients come from the four poles of
+//               planes of harmonic k;
+//   2. columns: one lane per (image column, k) runs the same recursions down
+//               the row-smoothed planes and demodulates with d_k: harmonic k's
+//               share of the numerator, cos S(f cos) + sin S(f sin), and of
+//               the denominator, cos S(cos) + sin S(sin), times d_k;
+//   3. one lane per pixel sums the K + 1 shares in float64 and divides.
+// The recursions' state and the phases are float64; the planes and shares
+// between the launches are float32.  The recursion coefficients come from the four poles of
 // Deriche's two damped cosine/sine pairs (his published fit of exp(-x^2/2)):
 // the causal half of the kernel is a sum of four one-pole terms, whose common
 // denominator and numerator give the recursion, and the anti-causal half
@@ -44,14 +44,13 @@ struct RecArgs {
   float* dst;
   int height, width, src_pitch, dst_pitch;
   int T;
-  int k;
-  int last;        // 1 on the last harmonic: write the quotient
-  double dk;       // d_k
+  int K;
   RecCoef c;
-  float* rows;     // 4 planes [4][height][width], row-smoothed
-  float* causal;   // 4 planes [4][height][width], causal part of the column pass
-  double* P;       // [height][width]
-  double* Q;       // [height][width]
+  float* rows;     // [K + 1][4][height][width], row-smoothed planes
+  float* causal;   // [K + 1][4][height][width], causal parts of the column pass
+  float* P;        // [K + 1][height][width], numerator shares
+  float* Q;        // [K + 1][height][width], denominator shares
+  double d[BF_MAX_K + 1];   // d_0..d_K
 };
 
 // Deriche's fit of exp(-x^2 / 2), x >= 0: two damped pairs
@@ -124,17 +123,18 @@ __device__ __forceinline__ void phase(float f, int k, int T, double* c, double* 
 
 __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a) {
   const int y = blockIdx.x * kLineThreads + threadIdx.x;
+  const int k = blockIdx.y;
   if (y >= a.height) return;
   const int L = a.width, M = a.c.margin;
   const size_t plane = (size_t)a.height * a.width;
   const float* frow = a.src + (size_t)y * a.src_pitch;
-  float* out = a.rows + (size_t)y * a.width;
+  float* out = a.rows + 4 * plane * k + (size_t)y * a.width;
   double xh[4][4] = {};  // x(i), x(i-1), x(i-2), x(i-3) per plane
   double yh[4][4] = {};  // y(i-1) .. y(i-4)
   for (int i = -M; i < L; ++i) {
     const float f = frow[fold(i, L)];
     double c, s;
-    phase(f, a.k, a.T, &c, &s);
+    phase(f, k, a.T, &c, &s);
     const double x[4] = {f * c, f * s, c, s};
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a)
   for (int i = L - 1 + M; i >= 0; --i) {
     const float f = frow[fold(i, L)];
     double c, s;
-    phase(f, a.k, a.T, &c, &s);
+    phase(f, k, a.T, &c, &s);
     const double x[4] = {f * c, f * s, c, s};
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
@@ -177,11 +177,13 @@ __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a)
 
 __global__ void __launch_bounds__(kLineThreads) rec_cols_kernel(const RecArgs a) {
   const int x0 = blockIdx.x * kLineThreads + threadIdx.x;
+  const int k = blockIdx.y;
   if (x0 >= a.width) return;
   const int L = a.height, M = a.c.margin, Wd = a.width;
   const size_t plane = (size_t)a.height * a.width;
-  const float* in = a.rows + x0;
-  float* cz = a.causal + x0;
+  const float* in = a.rows + 4 * plane * k + x0;
+  float* cz = a.causal + 4 * plane * k + x0;
+  const double dk = a.d[k];
   double xh[4][4] = {};
   double yh[4][4] = {};
   for (int i = -M; i < L; ++i) {
@@ -224,29 +226,33 @@ __global__ void __launch_bounds__(kLineThreads) rec_cols_kernel(const RecArgs a)
       for (int p = 0; p < 4; ++p) S[p] += cz[p * plane + r];
       const float f = a.src[(size_t)i * a.src_pitch + x0];
       double c, s;
-      phase(f, a.k, a.T, &c, &s);
-      const size_t o = (size_t)i * Wd + x0;
-      double pn = a.dk * (c * S[0] + s * S[1]);
-      double qn = a.dk * (c * S[2] + s * S[3]);
-      if (a.k > 0) {
-        pn += a.P[o];
-        qn += a.Q[o];
-      }
-      if (a.last) {
-        a.dst[(size_t)i * a.dst_pitch + x0] = static_cast<float>(pn / qn);
-      } else {
-        a.P[o] = pn;
-        a.Q[o] = qn;
-      }
+      phase(f, k, a.T, &c, &s);
+      const size_t o = plane * k + (size_t)i * Wd + x0;
+      a.P[o] = static_cast<float>(dk * (c * S[0] + s * S[1]));
+      a.Q[o] = static_cast<float>(dk * (c * S[2] + s * S[3]));
     }
   }
 }
 
+__global__ void __launch_bounds__(256) rec_sum_kernel(const RecArgs a) {
+  const size_t n = (size_t)a.height * a.width;
+  const size_t o = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (o >= n) return;
+  double p = 0.0, q = 0.0;
+  for (int k = 0; k <= a.K; ++k) {
+    p += a.P[n * k + o];
+    q += a.Q[n * k + o];
+  }
+  const int y = static_cast<int>(o / a.width), x = static_cast<int>(o % a.width);
+  a.dst[(size_t)y * a.dst_pitch + x] = static_cast<float>(p / q);
+}
+
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-size_t rec_ws_bytes(int height, int width) {
-  const size_t n = (size_t)height * width;
-  return 2 * align256(4 * n * sizeof(float)) + 2 * align256(n * sizeof(double));
+// layout: rows planes, causal planes, numerator shares, denominator shares
+size_t rec_ws_bytes(int height, int width, int K) {
+  const size_t n = (size_t)height * width, h = (size_t)K + 1;
+  return 2 * align256(4 * h * n * sizeof(float)) + 2 * align256(h * n * sizeof(float));
 }
 
 }  // namespace
@@ -254,15 +260,9 @@ size_t rec_ws_bytes(int height, int width) {
 
 using namespace bf;
 
-extern "C" size_t bf_recursive_workspace_bytes(int height, int width) {
-  if (height < 1 || width < 1) {
-    set_error("height and width must be >= 1");
-    return (size_t)-1;
-  }
-  return rec_ws_bytes(height, width);
-}
-
-extern "C" int bf_filter_recursive(const bf_job* job, void* workspace, size_t ws_bytes, void* hip_stream) {
+namespace {
+// checks of the recursive path on top of resolve_job's; BF_OK or a negative status
+int resolve_recursive(const bf_job* job, Resolved* r) {
   if (!job) return fail(BF_E_INVALID, "job is NULL");
   if (job->spatial != BF_SPATIAL_GAUSSIAN)
     return fail(BF_E_INVALID, "the recursive path smooths with a Gaussian: spatial must be BF_SPATIAL_GAUSSIAN");
@@ -272,15 +272,27 @@ extern "C" int bf_filter_recursive(const bf_job* job, void* workspace, size_t ws
   // validation and fit shared with bf_filter; the window does not apply here
   bf_job j = *job;
   j.W = 0;
+  return resolve_job(&j, r);
+}
+}  // namespace
+
+extern "C" size_t bf_recursive_workspace_bytes(const bf_job* job) {
   Resolved r;
-  const int rc = resolve_job(&j, &r);
+  if (resolve_recursive(job, &r) < 0) return (size_t)-1;
+  return rec_ws_bytes(job->height, job->width, r.desc.K);
+}
+
+extern "C" int bf_filter_recursive(const bf_job* job, void* workspace, size_t ws_bytes, void* hip_stream) {
+  Resolved r;
+  const int rc = resolve_recursive(job, &r);
   if (rc < 0) return rc;
+  const int K = r.desc.K;
   if (!workspace) return fail(BF_E_WORKSPACE, "workspace is NULL");
-  if (ws_bytes < rec_ws_bytes(job->height, job->width))
+  if (ws_bytes < rec_ws_bytes(job->height, job->width, K))
     return fail(BF_E_WORKSPACE, "workspace smaller than bf_recursive_workspace_bytes()");
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
     return fail(BF_E_WORKSPACE, "workspace must be 256-byte aligned");
-  const size_t n = (size_t)job->height * job->width;
+  const size_t n = (size_t)job->height * job->width, h = (size_t)K + 1;
   unsigned char* w = static_cast<unsigned char*>(workspace);
   RecArgs a{};
   a.src = job->src;
@@ -291,21 +303,19 @@ extern "C" int bf_filter_recursive(const bf_job* job, void* workspace, size_t ws
   a.dst_pitch = job->dst_pitch;
   a.T = job->T;
   a.c = recursion_coefficients(job->sigma_s);
+  a.K = K;
+  const size_t planes = align256(4 * h * n * sizeof(float)), shares = align256(h * n * sizeof(float));
   a.rows = reinterpret_cast<float*>(w);
-  a.causal = reinterpret_cast<float*>(w + align256(4 * n * sizeof(float)));
-  a.P = reinterpret_cast<double*>(w + 2 * align256(4 * n * sizeof(float)));
-  a.Q = reinterpret_cast<double*>(w + 2 * align256(4 * n * sizeof(float)) + align256(n * sizeof(double)));
+  a.causal = reinterpret_cast<float*>(w + planes);
+  a.P = reinterpret_cast<float*>(w + 2 * planes);
+  a.Q = reinterpret_cast<float*>(w + 2 * planes + shares);
+  for (int k = 0; k <= K; ++k) a.d[k] = r.desc.d[k];
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-  const int K = r.desc.K;
-  const dim3 grows((job->height + kLineThreads - 1) / kLineThreads);
-  const dim3 gcols((job->width + kLineThreads - 1) / kLineThreads);
-  for (int k = 0; k <= K; ++k) {
-    a.k = k;
-    a.dk = r.desc.d[k];
-    a.last = k == K ? 1 : 0;
-    hipLaunchKernelGGL(rec_rows_kernel, grows, dim3(kLineThreads), 0, stream, a);
-    hipLaunchKernelGGL(rec_cols_kernel, gcols, dim3(kLineThreads), 0, stream, a);
-  }
+  const dim3 grows((job->height + kLineThreads - 1) / kLineThreads, K + 1);
+  const dim3 gcols((job->width + kLineThreads - 1) / kLineThreads, K + 1);
+  hipLaunchKernelGGL(rec_rows_kernel, grows, dim3(kLineThreads), 0, stream, a);
+  hipLaunchKernelGGL(rec_cols_kernel, gcols, dim3(kLineThreads), 0, stream, a);
+  hipLaunchKernelGGL(rec_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(BF_E_DEVICE, std::string("recursive-filter launch failed: ") + hipGetErrorString(e));
   return r.status;

@@ -109,7 +109,7 @@ def _load():
     lib.bf_dynamic_range_workspace_bytes.restype = Z
     lib.bf_dynamic_range.argtypes = [P, I, I, I, I, P, P, Z, P]
     lib.bf_dynamic_range.restype = I
-    lib.bf_recursive_workspace_bytes.argtypes = [I, I]
+    lib.bf_recursive_workspace_bytes.argtypes = [jp]
     lib.bf_recursive_workspace_bytes.restype = Z
     lib.bf_filter_recursive.argtypes = [jp, P, Z, P]
     lib.bf_filter_recursive.restype = I
@@ -300,10 +300,10 @@ def bf_dynamic_range(src, W: int, T_out, workspace, ws_bytes: int, stream=None, 
                                        int(ws_bytes), _stream_handle(stream)))
 
 
-def bf_recursive_workspace_bytes(height: int, width: int) -> int:
-    n = lib.bf_recursive_workspace_bytes(int(height), int(width))
+def bf_recursive_workspace_bytes(job: Job) -> int:
+    n = lib.bf_recursive_workspace_bytes(ctypes.byref(job.struct))
     if n == ctypes.c_size_t(-1).value:
-        raise BfError(BF_E_INVALID, "height and width must be >= 1")
+        raise BfError(BF_E_INVALID, bf_last_error())
     return int(n)
 
 

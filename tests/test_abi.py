@@ -295,21 +295,20 @@ def test_batched_rejects_outputs_that_overlap_other_jobs():
 ])
 def test_recursive_filter_rejects_bad_jobs_before_device_work(kw, code):
     j = _job(**kw)
-    ws = native.bf_recursive_workspace_bytes(64, 64)
     with pytest.raises(native.BfError) as ei:
-        native.bf_filter_recursive(j, 0x30000000, ws, stream=0)
+        native.bf_filter_recursive(j, 0x30000000, 1 << 40, stream=0)
     assert ei.value.code == code
     assert native.bf_last_error()
+    with pytest.raises(native.BfError):
+        native.bf_recursive_workspace_bytes(j)
 
 
 def test_recursive_filter_workspace_checks():
-    # 48 bytes per pixel, each of the four regions 256-byte aligned
-    assert native.bf_recursive_workspace_bytes(64, 64) == 48 * 64 * 64
-    assert native.bf_recursive_workspace_bytes(3, 5) == 4 * 256
-    with pytest.raises(native.BfError):
-        native.bf_recursive_workspace_bytes(0, 5)
-    j = _job(W=0)
-    ws = native.bf_recursive_workspace_bytes(64, 64)
+    # 40 (K + 1) bytes per pixel, each of the four regions 256-byte aligned
+    j = _job(W=0, d=np.array([1.0, 0.5, 0.25]))
+    assert native.bf_recursive_workspace_bytes(j) == 40 * 3 * 64 * 64
+    assert native.bf_recursive_workspace_bytes(_job(W=0, d=np.array([1.0]), height=3, width=5)) == 4 * 256
+    ws = native.bf_recursive_workspace_bytes(j)
     for ptr, n in ((None, ws), (0x30000000, ws - 1), (0x30000004, ws)):
         with pytest.raises(native.BfError) as ei:
             native.bf_filter_recursive(j, ptr, n, stream=0)
