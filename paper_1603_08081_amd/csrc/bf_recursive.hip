@@ -1,7 +1,8 @@
 // Eq. (9) with the spatial convolutions of Algorithm 1 done by Deriche's
 // recursive Gaussian, the constant-time smoothing Sec. 2 cites.  Three
 // launches, the harmonics k = 0..K side by side in the grid (blockIdx.y):
-//   1. rows:    one lane per (image row, k) modulates f into the four planes
+//   1. rows:    one lane per (image row, k), 64 rows staged through LDS
+//               together, modulates f into the four planes
 //               f cos, f sin, cos, sin of k w f (w = pi / T) and runs the
 //               causal and anti-causal fourth-order recursions over the row
 //               (half-sample symmetric extension), writing the row-smoothed
@@ -121,57 +122,118 @@ __device__ __forceinline__ void phase(float f, int k, int T, double* c, double* 
   sincospi(a / T, s, c);
 }
 
+// The row pass goes through LDS in blocks of 64 rows x kChunk positions: the
+// wavefront loads and stores whole row segments (coalesced) while each lane
+// walks its own row inside the block.
+constexpr int kChunk = 32;
+constexpr int kTileStride = kChunk + 1;   // odd stride: a lane per row hits distinct banks
+
 __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a) {
-  const int y = blockIdx.x * kLineThreads + threadIdx.x;
+  __shared__ float ft[kLineThreads * kTileStride];       // f of the block
+  __shared__ float ot[4 * kLineThreads * kTileStride];   // the four planes of the block
+  const int lane = threadIdx.x;
+  const int y0 = blockIdx.x * kLineThreads;
   const int k = blockIdx.y;
-  if (y >= a.height) return;
   const int L = a.width, M = a.c.margin;
+  const int nrows = min(kLineThreads, a.height - y0);
   const size_t plane = (size_t)a.height * a.width;
-  const float* frow = a.src + (size_t)y * a.src_pitch;
-  float* out = a.rows + 4 * plane * k + (size_t)y * a.width;
+  float* outk = a.rows + 4 * plane * k;
+  // causal pass over positions -M .. L - 1
   double xh[4][4] = {};  // x(i), x(i-1), x(i-2), x(i-3) per plane
   double yh[4][4] = {};  // y(i-1) .. y(i-4)
-  for (int i = -M; i < L; ++i) {
-    const float f = frow[fold(i, L)];
-    double c, s;
-    phase(f, k, a.T, &c, &s);
-    const double x[4] = {f * c, f * s, c, s};
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      xh[p][3] = xh[p][2];
-      xh[p][2] = xh[p][1];
-      xh[p][1] = xh[p][0];
-      xh[p][0] = x[p];
-      const double v = a.c.nc[0] * xh[p][0] + a.c.nc[1] * xh[p][1] + a.c.nc[2] * xh[p][2] + a.c.nc[3] * xh[p][3] -
-                       a.c.dd[1] * yh[p][0] - a.c.dd[2] * yh[p][1] - a.c.dd[3] * yh[p][2] - a.c.dd[4] * yh[p][3];
-      yh[p][3] = yh[p][2];
-      yh[p][2] = yh[p][1];
-      yh[p][1] = yh[p][0];
-      yh[p][0] = v;
-      if (i >= 0) out[p * plane + i] = static_cast<float>(v);
+  for (int i0 = -M; i0 < L; i0 += kChunk) {
+    const int n = min(kChunk, L - i0);
+    if (lane < n) {
+      const int col = fold(i0 + lane, L);
+      for (int r = 0; r < nrows; ++r) ft[r * kTileStride + lane] = a.src[(size_t)(y0 + r) * a.src_pitch + col];
     }
+    __syncthreads();
+    if (lane < nrows) {
+      for (int j = 0; j < n; ++j) {
+        const float f = ft[lane * kTileStride + j];
+        double c, s;
+        phase(f, k, a.T, &c, &s);
+        const double x[4] = {f * c, f * s, c, s};
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          xh[p][3] = xh[p][2];
+          xh[p][2] = xh[p][1];
+          xh[p][1] = xh[p][0];
+          xh[p][0] = x[p];
+          const double v = a.c.nc[0] * xh[p][0] + a.c.nc[1] * xh[p][1] + a.c.nc[2] * xh[p][2] +
+                           a.c.nc[3] * xh[p][3] - a.c.dd[1] * yh[p][0] - a.c.dd[2] * yh[p][1] -
+                           a.c.dd[3] * yh[p][2] - a.c.dd[4] * yh[p][3];
+          yh[p][3] = yh[p][2];
+          yh[p][2] = yh[p][1];
+          yh[p][1] = yh[p][0];
+          yh[p][0] = v;
+          ot[(p * kLineThreads + lane) * kTileStride + j] = static_cast<float>(v);
+        }
+      }
+    }
+    __syncthreads();
+    if (lane < n && i0 + lane >= 0) {
+      for (int r = 0; r < nrows; ++r)
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          outk[p * plane + (size_t)(y0 + r) * L + i0 + lane] = ot[(p * kLineThreads + r) * kTileStride + lane];
+    }
+    __syncthreads();
   }
+  // anti-causal pass over positions L - 1 + M .. 0, blocks [lo, hi] from the top
   double xa[4][4] = {};  // x(i+1) .. x(i+4)
   double ya[4][4] = {};  // y(i+1) .. y(i+4)
-  for (int i = L - 1 + M; i >= 0; --i) {
-    const float f = frow[fold(i, L)];
-    double c, s;
-    phase(f, k, a.T, &c, &s);
-    const double x[4] = {f * c, f * s, c, s};
+  for (int hi = L - 1 + M; hi >= 0; hi -= kChunk) {
+    const int lo = max(hi - kChunk + 1, 0);
+    const int n = hi - lo + 1;
+    if (lane < n) {
+      const int i = lo + lane;
+      const int col = fold(i, L);
+      for (int r = 0; r < nrows; ++r) {
+        ft[r * kTileStride + lane] = a.src[(size_t)(y0 + r) * a.src_pitch + col];
+        if (i < L) {
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const double v = a.c.na[1] * xa[p][0] + a.c.na[2] * xa[p][1] + a.c.na[3] * xa[p][2] + a.c.na[4] * xa[p][3] -
-                       a.c.dd[1] * ya[p][0] - a.c.dd[2] * ya[p][1] - a.c.dd[3] * ya[p][2] - a.c.dd[4] * ya[p][3];
-      ya[p][3] = ya[p][2];
-      ya[p][2] = ya[p][1];
-      ya[p][1] = ya[p][0];
-      ya[p][0] = v;
-      xa[p][3] = xa[p][2];
-      xa[p][2] = xa[p][1];
-      xa[p][1] = xa[p][0];
-      xa[p][0] = x[p];
-      if (i < L) out[p * plane + i] = static_cast<float>(out[p * plane + i] + v);
+          for (int p = 0; p < 4; ++p)
+            ot[(p * kLineThreads + r) * kTileStride + lane] = outk[p * plane + (size_t)(y0 + r) * L + i];
+        }
+      }
     }
+    __syncthreads();
+    if (lane < nrows) {
+      for (int j = n - 1; j >= 0; --j) {
+        const float f = ft[lane * kTileStride + j];
+        double c, s;
+        phase(f, k, a.T, &c, &s);
+        const double x[4] = {f * c, f * s, c, s};
+        const bool inside = lo + j < L;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const double v = a.c.na[1] * xa[p][0] + a.c.na[2] * xa[p][1] + a.c.na[3] * xa[p][2] +
+                           a.c.na[4] * xa[p][3] - a.c.dd[1] * ya[p][0] - a.c.dd[2] * ya[p][1] -
+                           a.c.dd[3] * ya[p][2] - a.c.dd[4] * ya[p][3];
+          ya[p][3] = ya[p][2];
+          ya[p][2] = ya[p][1];
+          ya[p][1] = ya[p][0];
+          ya[p][0] = v;
+          xa[p][3] = xa[p][2];
+          xa[p][2] = xa[p][1];
+          xa[p][1] = xa[p][0];
+          xa[p][0] = x[p];
+          if (inside) {
+            float& o = ot[(p * kLineThreads + lane) * kTileStride + j];
+            o = static_cast<float>(o + v);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (lane < n && lo + lane < L) {
+      for (int r = 0; r < nrows; ++r)
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          outk[p * plane + (size_t)(y0 + r) * L + lo + lane] = ot[(p * kLineThreads + r) * kTileStride + lane];
+    }
+    __syncthreads();
   }
 }
 
