@@ -125,7 +125,7 @@ __device__ __forceinline__ void phase(float f, int k, int T, double* c, double* 
 // The row pass goes through LDS in blocks of 64 rows x kChunk positions: the
 // wavefront loads and stores whole row segments (coalesced) while each lane
 // walks its own row inside the block.
-constexpr int kChunk = 32;
+constexpr int kChunk = 16;
 constexpr int kTileStride = kChunk + 1;   // odd stride: a lane per row hits distinct banks
 
 __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a) {
