@@ -83,3 +83,20 @@ def test_close_to_the_truncated_gaussian_path_at_moderate_sigma():
     out, _ = _run(f, sigma_s=3.0, T=255, d=fit.d, integer_input=True)
     trunc = oracle.fourier(f, "gaussian", 3.0, 12, fit.d, 255)
     assert np.abs(out - trunc).max() < 0.1
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_full_frame_with_one_dimensional_structure(axis):
+    # at the benchmarked shape (2160 x 3840, sigma_s = 8, K = 32): an image
+    # constant along one axis is left as it is by the smoothing along that
+    # axis, so every line of the output is the 1-line filter of its profile
+    H, Wd = 2160, 3840
+    fit = oracle.fit_kernel("gaussian", 15.0, 255, 0.0, 32)
+    prof = np.random.default_rng(17).integers(0, 256, H if axis == 0 else Wd).astype(np.float32)
+    f = np.broadcast_to(prof[:, None] if axis == 0 else prof[None, :], (H, Wd))
+    print("recursive full frame, axis", axis, flush=True)
+    out, st = _run(f, sigma_s=8.0, T=255, d=fit.d, integer_input=True)
+    line = R.fourier_recursive(prof[:, None] if axis == 0 else prof[None, :], 8.0, fit.d, 255)
+    want = np.broadcast_to(line, (H, Wd))
+    assert st == 0
+    assert np.abs(out - want).max() <= TOL
