@@ -127,6 +127,8 @@ __device__ __forceinline__ void phase(float f, int k, int T, double* c, double* 
 // walks its own row inside the block.
 constexpr int kChunk = 16;
 constexpr int kTileStride = kChunk + 1;   // odd stride: a lane per row hits distinct banks
+constexpr int kRowsPerPass = kLineThreads / kChunk;   // rows one block transfer instruction covers
+static_assert(kLineThreads % kChunk == 0, "block transfers split the wavefront into whole row segments");
 
 __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a) {
   __shared__ float ft[kLineThreads * kTileStride];       // f of the block
@@ -138,14 +140,17 @@ __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a)
   const int nrows = min(kLineThreads, a.height - y0);
   const size_t plane = (size_t)a.height * a.width;
   float* outk = a.rows + 4 * plane * k;
+  // in block transfers lane = (row offset r0, position q)
+  const int q = lane % kChunk, r0 = lane / kChunk;
   // causal pass over positions -M .. L - 1
   double xh[4][4] = {};  // x(i), x(i-1), x(i-2), x(i-3) per plane
   double yh[4][4] = {};  // y(i-1) .. y(i-4)
   for (int i0 = -M; i0 < L; i0 += kChunk) {
     const int n = min(kChunk, L - i0);
-    if (lane < n) {
-      const int col = fold(i0 + lane, L);
-      for (int r = 0; r < nrows; ++r) ft[r * kTileStride + lane] = a.src[(size_t)(y0 + r) * a.src_pitch + col];
+    if (q < n) {
+      const int col = fold(i0 + q, L);
+      for (int r = r0; r < nrows; r += kRowsPerPass)
+        ft[r * kTileStride + q] = a.src[(size_t)(y0 + r) * a.src_pitch + col];
     }
     __syncthreads();
     if (lane < nrows) {
@@ -172,11 +177,11 @@ __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a)
       }
     }
     __syncthreads();
-    if (lane < n && i0 + lane >= 0) {
-      for (int r = 0; r < nrows; ++r)
+    if (q < n && i0 + q >= 0) {
+      for (int r = r0; r < nrows; r += kRowsPerPass)
 #pragma unroll
         for (int p = 0; p < 4; ++p)
-          outk[p * plane + (size_t)(y0 + r) * L + i0 + lane] = ot[(p * kLineThreads + r) * kTileStride + lane];
+          outk[p * plane + (size_t)(y0 + r) * L + i0 + q] = ot[(p * kLineThreads + r) * kTileStride + q];
     }
     __syncthreads();
   }
@@ -186,15 +191,15 @@ __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a)
   for (int hi = L - 1 + M; hi >= 0; hi -= kChunk) {
     const int lo = max(hi - kChunk + 1, 0);
     const int n = hi - lo + 1;
-    if (lane < n) {
-      const int i = lo + lane;
+    if (q < n) {
+      const int i = lo + q;
       const int col = fold(i, L);
-      for (int r = 0; r < nrows; ++r) {
-        ft[r * kTileStride + lane] = a.src[(size_t)(y0 + r) * a.src_pitch + col];
+      for (int r = r0; r < nrows; r += kRowsPerPass) {
+        ft[r * kTileStride + q] = a.src[(size_t)(y0 + r) * a.src_pitch + col];
         if (i < L) {
 #pragma unroll
           for (int p = 0; p < 4; ++p)
-            ot[(p * kLineThreads + r) * kTileStride + lane] = outk[p * plane + (size_t)(y0 + r) * L + i];
+            ot[(p * kLineThreads + r) * kTileStride + q] = outk[p * plane + (size_t)(y0 + r) * L + i];
         }
       }
     }
@@ -227,11 +232,11 @@ __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a)
       }
     }
     __syncthreads();
-    if (lane < n && lo + lane < L) {
-      for (int r = 0; r < nrows; ++r)
+    if (q < n && lo + q < L) {
+      for (int r = r0; r < nrows; r += kRowsPerPass)
 #pragma unroll
         for (int p = 0; p < 4; ++p)
-          outk[p * plane + (size_t)(y0 + r) * L + lo + lane] = ot[(p * kLineThreads + r) * kTileStride + lane];
+          outk[p * plane + (size_t)(y0 + r) * L + lo + q] = ot[(p * kLineThreads + r) * kTileStride + q];
     }
     __syncthreads();
   }
