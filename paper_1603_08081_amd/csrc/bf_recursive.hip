@@ -12,8 +12,10 @@
 //               share of the numerator, cos S(f cos) + sin S(f sin), and of
 //               the denominator, cos S(cos) + sin S(sin), times d_k;
 //   3. one lane per pixel sums the K + 1 shares in float64 and divides.
-// The recursions' state and the phases are float64; the planes and shares
-// between the launches are float32.  The recursion coefficients come from the four poles of
+// The recursions' state is float64; the phases are float64, except in the
+// row pass of integer images, which looks cos and sin of pi m / T up in a
+// float32 table (m = k f mod 2T); the planes and shares between the launches
+// are float32.  The recursion coefficients come from the four poles of
 // Deriche's two damped cosine/sine pairs (his published fit of exp(-x^2/2)):
 // the causal half of the kernel is a sum of four one-pole terms, whose common
 // denominator and numerator give the recursion, and the anti-causal half
@@ -46,6 +48,7 @@ struct RecArgs {
   int height, width, src_pitch, dst_pitch;
   int T;
   int K;
+  int integer;     // BF_FLAG_INTEGER_INPUT: phases of the row pass from a table
   RecCoef c;
   float* rows;     // [K + 1][4][height][width], row-smoothed planes
   float* causal;   // [K + 1][4][height][width], causal parts of the column pass
@@ -130,9 +133,19 @@ constexpr int kTileStride = kChunk + 1;   // odd stride: a lane per row hits dis
 constexpr int kRowsPerPass = kLineThreads / kChunk;   // rows one block transfer instruction covers
 static_assert(kLineThreads % kChunk == 0, "block transfers split the wavefront into whole row segments");
 
+// cos and sin of pi m / T for m = k f mod 2T, f an integer gray level; the
+// index is reduced into [0, 2T) whatever f holds
+__device__ __forceinline__ float2 phase_tab(const float2* tab, float f, int k, int T) {
+  const int T2 = 2 * T;
+  const float fc = fminf(fmaxf(f, 0.0f), 1.0e6f);
+  int m = static_cast<int>((static_cast<long long>(k) * static_cast<long long>(fc)) % T2);
+  return tab[m];
+}
+
 __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a) {
   __shared__ float ft[kLineThreads * kTileStride];       // f of the block
   __shared__ float ot[4 * kLineThreads * kTileStride];   // the four planes of the block
+  extern __shared__ float2 cs_tab[];                     // 2T entries (cos, sin) when a.integer
   const int lane = threadIdx.x;
   const int y0 = blockIdx.x * kLineThreads;
   const int k = blockIdx.y;
@@ -142,6 +155,14 @@ __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a)
   float* outk = a.rows + 4 * plane * k;
   // in block transfers lane = (row offset r0, position q)
   const int q = lane % kChunk, r0 = lane / kChunk;
+  if (a.integer) {
+    for (int m = lane; m < 2 * a.T; m += kLineThreads) {
+      double c, s;
+      sincospi(static_cast<double>(m) / a.T, &s, &c);
+      cs_tab[m] = make_float2(static_cast<float>(c), static_cast<float>(s));
+    }
+  }
+  __syncthreads();
   // causal pass over positions -M .. L - 1
   double xh[4][4] = {};  // x(i), x(i-1), x(i-2), x(i-3) per plane
   double yh[4][4] = {};  // y(i-1) .. y(i-4)
@@ -157,7 +178,13 @@ __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a)
       for (int j = 0; j < n; ++j) {
         const float f = ft[lane * kTileStride + j];
         double c, s;
-        phase(f, k, a.T, &c, &s);
+        if (a.integer) {
+          const float2 cs = phase_tab(cs_tab, f, k, a.T);
+          c = cs.x;
+          s = cs.y;
+        } else {
+          phase(f, k, a.T, &c, &s);
+        }
         const double x[4] = {f * c, f * s, c, s};
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
@@ -208,7 +235,13 @@ __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a)
       for (int j = n - 1; j >= 0; --j) {
         const float f = ft[lane * kTileStride + j];
         double c, s;
-        phase(f, k, a.T, &c, &s);
+        if (a.integer) {
+          const float2 cs = phase_tab(cs_tab, f, k, a.T);
+          c = cs.x;
+          s = cs.y;
+        } else {
+          phase(f, k, a.T, &c, &s);
+        }
         const double x[4] = {f * c, f * s, c, s};
         const bool inside = lo + j < L;
 #pragma unroll
@@ -369,6 +402,7 @@ extern "C" int bf_filter_recursive(const bf_job* job, void* workspace, size_t ws
   a.src_pitch = job->src_pitch;
   a.dst_pitch = job->dst_pitch;
   a.T = job->T;
+  a.integer = (job->flags & BF_FLAG_INTEGER_INPUT) ? 1 : 0;
   a.c = recursion_coefficients(job->sigma_s);
   a.K = K;
   const size_t planes = align256(4 * h * n * sizeof(float)), shares = align256(h * n * sizeof(float));
@@ -380,7 +414,8 @@ extern "C" int bf_filter_recursive(const bf_job* job, void* workspace, size_t ws
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
   const dim3 grows((job->height + kLineThreads - 1) / kLineThreads, K + 1);
   const dim3 gcols((job->width + kLineThreads - 1) / kLineThreads, K + 1);
-  hipLaunchKernelGGL(rec_rows_kernel, grows, dim3(kLineThreads), 0, stream, a);
+  const size_t tab_bytes = a.integer ? 2 * (size_t)job->T * sizeof(float2) : 0;
+  hipLaunchKernelGGL(rec_rows_kernel, grows, dim3(kLineThreads), tab_bytes, stream, a);
   hipLaunchKernelGGL(rec_cols_kernel, gcols, dim3(kLineThreads), 0, stream, a);
   hipLaunchKernelGGL(rec_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a);
   const hipError_t e = hipGetLastError();
