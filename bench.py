@@ -38,13 +38,29 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    """The host CPU's model name (first entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def alg_flops_per_px(K, W, spatial="gaussian"):
-    """Separable smoothing of the 4K+1 planes: two passes of 2W+1 MACs each
-    for the Gaussian; for the box, whose passes are running sums, one add
-    and one subtract per plane and pass."""
+    """Algorithmic flops per output pixel: the separable smoothing of the
+    4K+1 planes (two passes of 2W+1 multiply-adds each for the Gaussian; for
+    the box, whose passes are running sums, one add and one subtract per
+    plane and pass) plus 16 per harmonic for the modulation ((f - c0) cos and
+    (f - c0) sin, d_k cos and d_k sin) and the demodulation (two
+    multiply-adds each into the numerator and the denominator)."""
+    mod_demod = 16 * K
     if spatial == "box":
-        return (4 * K + 1) * 2 * 2
-    return (4 * K + 1) * 2 * (2 * W + 1) * 2
+        return (4 * K + 1) * 2 * 2 + mod_demod
+    return (4 * K + 1) * 2 * (2 * W + 1) * 2 + mod_demod
 
 
 def issued_flops_per_px(K, W, tile_rows):
@@ -236,10 +252,19 @@ def run_recursive(args):
             "config": {"workload": "%s, first frame (%d x %d), recursive Gaussian sigma_s = %g, %s range "
                                    "sigma_r = %g, K = %d" % (args.workload, H, Wd, wl["sigma_s"],
                                                              wl["range_kind"], wl["sigma_r"], K)},
-            "roofline": {"bound": "alu", "achieved": round(fl, 2), "peak": PEAK_FP64_VECTOR_TFLOPS,
-                         "unit": "TFLOP/s", "frac": round(fl / PEAK_FP64_VECTOR_TFLOPS, 4), "traffic": None,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
                          "kernel": "rec_rows_kernel + rec_cols_kernel + rec_sum_kernel, 3 launches per step",
-                         "plane_bytes_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}}
+                         "bytes_per_px": recursive_bytes_per_px(K),
+                         "fp64_tflops": round(fl, 2), "fp64_frac": round(fl / PEAK_FP64_VECTOR_TFLOPS, 4)}}
+    if not args.no_check:
+        import oracle.recursive as orec
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        d = native.bf_fit_coeffs(wl["range_kind"], wl["sigma_r"], wl["T"], wl["eps"], wl["K_max"])[1]
+        ref = orec.fourier_recursive(img.astype(np.float64), wl["sigma_s"], d, wl["T"])
+        line["max_err_vs_oracle_recursive_fp64"] = float("%.4g" % np.abs(got - ref).max())
+        line["err_sample"] = "every pixel"
     print(json.dumps(line))
 
 
@@ -515,9 +540,22 @@ def main():
             used.append("%d rows of image %d" % (nr, i))
             if spent >= args.cpu_seconds * 0.95:
                 break
-        cpu = {"value": round(done_px / spent / 1e6, 4), "unit": "Mpix/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": "eq. (9) in FP64 on %s (%d px), %.1f s" % (", ".join(used), done_px, spent)}
+        # single-thread rate of the same oracle on the first rows of image 0
+        nthreads = oracle.num_threads()
+        prev = oracle.set_threads(1)
+        W0 = imgs[0].shape[1]
+        t1 = time.time()
+        n1 = 0
+        while time.time() - t1 < min(3.0, args.cpu_seconds / 5):
+            ora(0, np.arange(n1 * W0, (n1 + 1) * W0))
+            n1 += 1
+        t_single = time.time() - t1
+        oracle.set_threads(prev)
+        cpu = {"value": round(done_px / spent / 1e6, 4), "unit": "Mpix/s", "cores": nthreads,
+               "kind": "oracle", "cpu_model": cpu_model(),
+               "single_thread_value": round(n1 * W0 / t_single / 1e6, 5),
+               "sample": "eq. (9) in FP64 on %s (%d px), %.1f s; single thread: %d rows of image 0, %.1f s"
+                         % (", ".join(used), done_px, spent, n1, t_single)}
 
     if uniform:
         H, Wd = imgs[0].shape

@@ -68,7 +68,9 @@ typedef enum {
 typedef enum {
   BF_PLANES_FP32 = 0,        /* planes, smoothing and accumulation in float32 */
   BF_PLANES_FP16 = 1,        /* planes and smoothing operands in float16 (RNE), float32 accumulation */
-  BF_PLANES_BF16 = 2         /* planes and smoothing operands in bfloat16 (RNE), float32 accumulation */
+  BF_PLANES_BF16 = 2         /* modulated planes and row-pass weights in bfloat16 (RNE); the
+                                row-smoothed planes and column-pass weights in float16 (RNE);
+                                float32 accumulation */
 } bf_planes;
 
 /* flags of bf_job.flags */
@@ -76,6 +78,12 @@ typedef enum {
                                    (f_max = T unless set): enables the exact table-only phase
                                    path.  With the flag set, a pixel outside that contract makes
                                    the outputs whose windows contain it unspecified. */
+#define BF_FLAG_OFFSETS16 2     /* schedule only (no result bit changes): with 16-bit planes on
+                                   integer images, stage 16-bit gray-level table offsets instead
+                                   of 32-bit table addresses (the latter are used when the gray
+                                   levels fit 256 table entries and the tile fits LDS).  In a
+                                   batched call or plan it applies to the whole kernel class of
+                                   the job. */
 
 /*
  * bf_fit_coeffs -- Algorithm 2 (Sec. 3), on the host, in float64.
@@ -323,18 +331,14 @@ int bf_filter_recursive(const bf_job* job, void* workspace, size_t ws_bytes, voi
 const char* bf_last_error(void);
 
 /*
- * Environment variables (schedule only: none of them changes a result bit).
+ * Environment variables (schedule only: none of them changes a result bit;
+ * both are read when a plan or batched call is created, never per launch).
  *   BF_TILE_ROWS=32|64|96|128|144  preferred output-tile height of new plans and
  *                  batched calls (a class takes the tallest height not above
  *                  it that all its jobs support); read at plan creation.
  *   BF_BATCH_GRID=items|<n>    workgroups per class launch: one per tile, or
  *                  a fixed n; unset = a persistent grid sized by occupancy;
  *                  read at plan creation.
- *   BF_WAVE_NARROW=1           16-bit planes on integer images: stage 16-bit
- *                  table offsets instead of 32-bit table addresses (the
- *                  latter are used when the gray levels fit 256 table entries
- *                  and the tile fits LDS); read at each launch, and captured
- *                  with a plan's graph.
  * While either of the first two is set, remembered tuner choices are not
  * applied at plan creation; bf_plan_tune still times and sets the geometry.
  */

@@ -20,7 +20,7 @@ from .fit import (  # noqa: F401
     FitResult, accuracy_bound, back_substitute, fit_kernel, progressive_fit, sample_kernel, series,
 )
 from .filters import (  # noqa: F401
-    brute_direct, build, center_weight, direct, fourier, num_threads, shiftable_alg1,
+    brute_direct, build, center_weight, direct, fourier, num_threads, set_threads, shiftable_alg1,
     spatial_profile,
 )
 from .dynamic_range import brute_local_dynamic_range, local_dynamic_range  # noqa: F401,E402

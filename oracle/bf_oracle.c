@@ -40,6 +40,16 @@ int oracle_num_threads(void) {
 #endif
 }
 
+/* Sets the number of threads later calls use (n >= 1); returns the previous
+   number.  Only the timing of the CPU baseline changes it. */
+int oracle_set_threads(int n) {
+  const int prev = oracle_num_threads();
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#endif
+  return prev;
+}
+
 /* half-sample symmetric reflection of an index into [0, n) (one fold) */
 static long reflect(long i, long n) {
   if (i < 0) return -i - 1;

@@ -57,12 +57,19 @@ def _load():
             lib.oracle_center_weight.restype = D
             lib.oracle_num_threads.argtypes = []
             lib.oracle_num_threads.restype = I
+            lib.oracle_set_threads.argtypes = [I]
+            lib.oracle_set_threads.restype = I
             _lib = lib
     return _lib
 
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_threads(n: int) -> int:
+    """Threads of later oracle calls (n >= 1); returns the previous count."""
+    return int(_load().oracle_set_threads(int(n)))
 
 
 def center_weight(spatial: str, sigma_s: float, W: int) -> float:

@@ -160,6 +160,7 @@ int build_plan(const bf_job* jobs, int n_jobs, bf_planes prec, PlanData& p) {
       c.nt = nt;
       c.family = base.family;
       c.tc = base;
+      c.tc.offsets16 = false;
       for (int th : {32, 64, 96, 128, 144}) {
         const TileChoice t = choose_tile(r.desc, prec, th);
         if (t.th == th && t.family == base.family) c.th_options.push_back(th);
@@ -173,6 +174,7 @@ int build_plan(const bf_job* jobs, int n_jobs, bf_planes prec, PlanData& p) {
       c.th_options = keep;
     }
     c.jobs.push_back(i);
+    c.tc.offsets16 = c.tc.offsets16 || base.offsets16;
     c.t_max = std::max(c.t_max, r.desc.T);
     c.f_max = std::max(c.f_max, r.desc.F);
     c.px += (double)r.desc.height * r.desc.width;

@@ -63,8 +63,24 @@ struct Planes<BF_PLANES_FP32> {
   static __device__ __forceinline__ float round(float x) { return x; }
 };
 
+// 16-bit formats.  E / V8 / V4 / mma / round: the modulated planes and the
+// row-pass weights (the plane format).  RE / RV8 / RV4 / mma_col / round_col:
+// the row-smoothed intermediate and the column-pass weights, which are
+// float16 for both formats -- rounding that intermediate is the larger of
+// bfloat16's two error sources, and its 8-bit mantissa alone keeps the
+// result well away from half a gray level on the UHD workload.
+struct RingF16 {
+  using RE = _Float16;
+  using RV8 = f16x8;
+  using RV4 = f16x4;
+  static __device__ __forceinline__ float round_col(float x) { return (float)(_Float16)x; }
+  static __device__ __forceinline__ f32x4 mma_col(RV8 a, RV8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
 template <>
-struct Planes<BF_PLANES_FP16> {
+struct Planes<BF_PLANES_FP16> : RingF16 {
   using E = _Float16;
   using V8 = f16x8;
   using V4 = f16x4;
@@ -78,7 +94,7 @@ struct Planes<BF_PLANES_FP16> {
 };
 
 template <>
-struct Planes<BF_PLANES_BF16> {
+struct Planes<BF_PLANES_BF16> : RingF16 {
   using E = __bf16;
   using V8 = b16x8;
   using V4 = b16x4;
@@ -90,6 +106,11 @@ struct Planes<BF_PLANES_BF16> {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
 };
+
+// the 16-bit traits of a format (fp32 maps to fp16; only used in branches
+// that fp32 planes never take)
+template <int PREC>
+using PlanesOr16 = Planes<PREC == BF_PLANES_FP32 ? BF_PLANES_FP16 : PREC>;
 
 // Tile geometry shared by the kernel and its launcher.
 template <int PREC, int NT>
@@ -229,6 +250,12 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
   __syncthreads();
 
   auto wq = [&](int dd) -> float { return (dd >= -W && dd <= W) ? PT::round(w1s[dd + W]) : 0.f; };
+  // column-pass weights: rounded like the row-smoothed intermediate (float16)
+  // for 16-bit planes, unrounded for fp32
+  auto wqc = [&](int dd) -> float {
+    if constexpr (F32) return wq(dd);
+    else return (dd >= -W && dd <= W) ? PlanesOr16<PREC>::round_col(w1s[dd + W]) : 0.f;
+  };
 
   // Toeplitz operands.  Row pass: B[k][n] = w(input col - output col), the
   // input col of contraction slot k counted from x0 - Wal.  Column pass: the
@@ -237,9 +264,10 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
   // counted from the output row - W.
   using BrowT = std::conditional_t<F32, float, typename std::conditional_t<F32, Planes<BF_PLANES_FP16>, PT>::V8>;
   constexpr int NBR = F32 ? 8 * KS : KS;
+  using BcolT = std::conditional_t<F32, float, typename std::conditional_t<F32, Planes<BF_PLANES_FP16>, PT>::RV8>;
   BrowT brow[NBR];
   float bcol32[F32 ? NT : 1][4];
-  BrowT bcol16[F32 ? 1 : KS];
+  BcolT bcol16[F32 ? 1 : KS];
   if constexpr (F32) {
     for (int s4 = 0; s4 < NBR; ++s4) brow[s4] = wq(4 * s4 + g - Wal - n16);
     for (int t = 0; t < NT; ++t)
@@ -248,15 +276,20 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
     for (int ks = 0; ks < KS; ++ks)
       for (int e = 0; e < 8; ++e) {
         brow[ks][e] = (E)wq(32 * ks + 8 * g + e - Wal - n16);
-        bcol16[ks][e] = (E)wq(16 * (2 * ks + (e >> 2)) + 4 * g + (e & 3) - W - n16);
+        bcol16[ks][e] = (typename PlanesOr16<PREC>::RE)wqc(16 * (2 * ks + (e >> 2)) + 4 * g + (e & 3) - W - n16);
       }
   }
   // fp32 planes accumulate P and Q in float64 (see the column pass below);
   // 16-bit planes are limited by their own rounding and accumulate in float32
   using Acc = std::conditional_t<F32, double, float>;
-  double wsum = 0.0;
-  for (int t = -W; t <= W; ++t) wsum += (double)wq(t);
-  const Acc q0 = (Acc)(job.d[0] * wsum * wsum);
+  // k = 0: Q gains d_0 times the smoothing of the ones-plane, i.e. the
+  // product of the row and column weight sums
+  double wsum_r = 0.0, wsum_c = 0.0;
+  for (int t = -W; t <= W; ++t) {
+    wsum_r += (double)wq(t);
+    wsum_c += (double)wqc(t);
+  }
+  const Acc q0 = (Acc)(job.d[0] * wsum_r * wsum_c);
 
   // general path: gray levels at this lane's output pixels (row Y0 + 16 j + n16, cols x0 + 4 g + i)
   float fo[INTEGER ? 1 : NJ][4];
@@ -274,7 +307,7 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
   const PhaseTab pt{lut, 2.f * (float)T, 1.f / (2.f * (float)T), 1.f / (float)T, 2 * T};
   const float two_t = 2.f * (float)T, inv_two_t = 1.f / (2.f * (float)T);
 
-  using RingT = std::conditional_t<F32, f32x4, typename std::conditional_t<F32, Planes<BF_PLANES_FP16>, PT>::V4>;
+  using RingT = std::conditional_t<F32, f32x4, typename std::conditional_t<F32, Planes<BF_PLANES_FP16>, PT>::RV4>;
 
   for (int k = 0; k <= K; ++k) {
     const float kf = (float)k;
@@ -422,8 +455,8 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
               __builtin_memcpy(&a, &planes[b][p][n16][16 * wave + 32 * ks + 8 * g], sizeof(a));
               acc = PT::mma(a, brow[ks], acc);
             }
-            typename PT::V4 v;
-            for (int i = 0; i < 4; ++i) v[i] = (E)acc[i];
+            RingT v;
+            for (int i = 0; i < 4; ++i) v[i] = (typename PlanesOr16<PREC>::RE)acc[i];
             ring[s % NT][pi] = v;
           }
         }
@@ -455,12 +488,14 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
               f32x4 acc = {0.f, 0.f, 0.f, 0.f};
               static_for<0, KS>([&](auto kc) {
                 constexpr int ks = decltype(kc)::value;
-                typename PT::V4 lo = ring[(j + 2 * ks) % NT][pi];
-                typename PT::V4 hi;
+                using R16 = PlanesOr16<PREC>;
+                typename R16::RV4 lo = ring[(j + 2 * ks) % NT][pi];
+                typename R16::RV4 hi;
                 if constexpr (2 * ks + 1 < NT) hi = ring[(j + 2 * ks + 1) % NT][pi];
-                else hi = typename PT::V4{(E)0.f, (E)0.f, (E)0.f, (E)0.f};
-                typename PT::V8 a = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
-                acc = PT::mma(a, bcol16[ks], acc);
+                else hi = typename R16::RV4{(typename R16::RE)0.f, (typename R16::RE)0.f, (typename R16::RE)0.f,
+                                            (typename R16::RE)0.f};
+                typename R16::RV8 a = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+                acc = R16::mma_col(a, bcol16[ks], acc);
               });
 #pragma unroll
               for (int i = 0; i < 4; ++i) fb[pi][i] = acc[i];

@@ -57,6 +57,7 @@ hipError_t launch_fused(const JobDesc& job, bf_planes prec, int th, hipStream_t 
 // wave kernel, 2 = shared-plane kernel with staged tile, 0 = general path.
 struct TileChoice {
   int cols, th, family;
+  bool offsets16;  // wave kernel: stage 16-bit table offsets (BF_FLAG_OFFSETS16 on a job of the class)
 };
 TileChoice choose_tile(const JobDesc& job, bf_planes prec, int th_pref);
 // one persistent launch over n_items work items (int4: job, x0, y0, -) that

@@ -16,8 +16,6 @@
 // to the plane format (8 bytes); the demodulation table holds d_k cos and
 // d_k sin in fp32.  A row-pass operand is one 8-byte gather per pixel and
 // two byte permutes per pixel pair and plane pair.
-#include <cstdlib>
-
 #include "bf_fused_impl.h"
 
 namespace bf {
@@ -33,19 +31,9 @@ __device__ __forceinline__ uint32_t hi_halves(uint32_t a, uint32_t b) {
   return __builtin_amdgcn_perm(b, a, 0x07060302u);
 }
 
-#ifndef BF_WAVE_NW
-#define BF_WAVE_NW 8
-#endif
-constexpr int kWaveNW = BF_WAVE_NW;              // waves per workgroup
+constexpr int kWaveNW = 8;                       // waves per workgroup
 constexpr int kWaveThreads = 64 * kWaveNW;
 constexpr int kWaveCols = 16 * kWaveNW;          // output columns per tile
-
-// optional register budget of the wave kernels (waves per SIMD)
-#ifdef BF_WAVE_MIN_WAVES
-#define BF_WAVE_OCC __attribute__((amdgpu_waves_per_eu(BF_WAVE_MIN_WAVES)))
-#else
-#define BF_WAVE_OCC
-#endif
 
 template <int PREC, int NT>
 struct WaveGeo {
@@ -113,6 +101,7 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
   using G = WaveGeo<PREC, NT>;
   using PT = Planes<PREC>;
   using E = typename PT::E;
+  using RE = typename PT::RE;
   constexpr int KS = G::KS, LWU = G::LWU, FW = G::FW, MODB = G::MODB;
   constexpr int NJ = TH / 16, NS = NJ + NT - 1, FROWS = 16 * NS;
   auto ftile = reinterpret_cast<uint16_t(*)[FW]>(ftile_raw);
@@ -146,15 +135,21 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
   __syncthreads();
 
   auto wq = [&](int dd) -> float { return (dd >= -W && dd <= W) ? PT::round(w1s[dd + W]) : 0.f; };
-  typename PT::V8 brow[KS], bcol[KS];
+  auto wqc = [&](int dd) -> float { return (dd >= -W && dd <= W) ? PT::round_col(w1s[dd + W]) : 0.f; };
+  typename PT::V8 brow[KS];
+  typename PT::RV8 bcol[KS];
   for (int ks = 0; ks < KS; ++ks)
     for (int e = 0; e < 8; ++e) {
       brow[ks][e] = (E)wq(32 * ks + 8 * g + e - Wal - n16);
-      bcol[ks][e] = (E)wq(16 * (2 * ks + (e >> 2)) + 4 * g + (e & 3) - W - n16);
+      bcol[ks][e] = (RE)wqc(16 * (2 * ks + (e >> 2)) + 4 * g + (e & 3) - W - n16);
     }
-  double wsum = 0.0;
-  for (int t = -W; t <= W; ++t) wsum += (double)wq(t);
-  const float q0 = (float)(job.d[0] * wsum * wsum);
+  // k = 0: Q gains d_0 (sum of row weights) (sum of column weights)
+  double wsum_r = 0.0, wsum_c = 0.0;
+  for (int t = -W; t <= W; ++t) {
+    wsum_r += (double)wq(t);
+    wsum_c += (double)wqc(t);
+  }
+  const float q0 = (float)(job.d[0] * wsum_r * wsum_c);
   float P[NJ][4], Q[NJ][4];
   for (int j = 0; j < NJ; ++j)
     for (int i = 0; i < 4; ++i) P[j][i] = Q[j][i] = 0.f;
@@ -187,7 +182,7 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
     const float dk = (float)job.d[k];
     auto run = [&](auto nplc) {
       constexpr int NPL = decltype(nplc)::value;  // 1 for k = 0 (plane f - c0 only), else 4
-      typename PT::V4 ring[NT][NPL];
+      typename PT::RV4 ring[NT][NPL];
       // gray-level offsets of one step (read one step ahead) and, for the
       // four-plane harmonics, the gathered entries of two steps: the table
       // gathers of step s + 1 are issued before the permutes and MFMAs of
@@ -264,8 +259,8 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
         }
 #pragma unroll
         for (int pi = 0; pi < NPL; ++pi) {
-          typename PT::V4 v;
-          for (int i = 0; i < 4; ++i) v[i] = (E)racc[pi][i];
+          typename PT::RV4 v;
+          for (int i = 0; i < 4; ++i) v[i] = (RE)racc[pi][i];
           ring[s % NT][pi] = v;
         }
         // ---- column pass + demodulation of output tile j = s - NT + 1
@@ -277,12 +272,12 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
             static_for<0, KS>([&](auto kc) {
               constexpr int ks = decltype(kc)::value;
-              typename PT::V4 lo = ring[(j + 2 * ks) % NT][pi];
-              typename PT::V4 hi;
+              typename PT::RV4 lo = ring[(j + 2 * ks) % NT][pi];
+              typename PT::RV4 hi;
               if constexpr (2 * ks + 1 < NT) hi = ring[(j + 2 * ks + 1) % NT][pi];
-              else hi = typename PT::V4{(E)0.f, (E)0.f, (E)0.f, (E)0.f};
-              typename PT::V8 a = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
-              acc = PT::mma(a, bcol[ks], acc);
+              else hi = typename PT::RV4{(RE)0.f, (RE)0.f, (RE)0.f, (RE)0.f};
+              typename PT::RV8 a = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+              acc = PT::mma_col(a, bcol[ks], acc);
             });
             for (int i = 0; i < 4; ++i) fb[pi][i] = acc[i];
           }
@@ -333,6 +328,7 @@ __device__ __forceinline__ void wave_tile_wide(const JobDesc& job, int X0, int Y
   using L = WideLds<PREC, NT, TH>;
   using PT = Planes<PREC>;
   using E = typename PT::E;
+  using RE = typename PT::RE;
   constexpr int KS = G::KS, LWU = G::LWU, FW = L::FW, MODB = G::MODB, SPAN = kWideSpan;
   constexpr int NJ = TH / 16, NS = NJ + NT - 1, FROWS = 16 * NS;
   auto ftile = reinterpret_cast<uint32_t(*)[FW]>(ftile_raw);
@@ -366,15 +362,21 @@ __device__ __forceinline__ void wave_tile_wide(const JobDesc& job, int X0, int Y
   __syncthreads();
 
   auto wq = [&](int dd) -> float { return (dd >= -W && dd <= W) ? PT::round(w1s[dd + W]) : 0.f; };
-  typename PT::V8 brow[KS], bcol[KS];
+  auto wqc = [&](int dd) -> float { return (dd >= -W && dd <= W) ? PT::round_col(w1s[dd + W]) : 0.f; };
+  typename PT::V8 brow[KS];
+  typename PT::RV8 bcol[KS];
   for (int ks = 0; ks < KS; ++ks)
     for (int e = 0; e < 8; ++e) {
       brow[ks][e] = (E)wq(32 * ks + 8 * g + e - Wal - n16);
-      bcol[ks][e] = (E)wq(16 * (2 * ks + (e >> 2)) + 4 * g + (e & 3) - W - n16);
+      bcol[ks][e] = (RE)wqc(16 * (2 * ks + (e >> 2)) + 4 * g + (e & 3) - W - n16);
     }
-  double wsum = 0.0;
-  for (int t = -W; t <= W; ++t) wsum += (double)wq(t);
-  const float q0 = (float)(job.d[0] * wsum * wsum);
+  // k = 0: Q gains d_0 (sum of row weights) (sum of column weights)
+  double wsum_r = 0.0, wsum_c = 0.0;
+  for (int t = -W; t <= W; ++t) {
+    wsum_r += (double)wq(t);
+    wsum_c += (double)wqc(t);
+  }
+  const float q0 = (float)(job.d[0] * wsum_r * wsum_c);
   float P[NJ][4], Q[NJ][4];
   for (int j = 0; j < NJ; ++j)
     for (int i = 0; i < 4; ++i) P[j][i] = Q[j][i] = 0.f;
@@ -400,7 +402,7 @@ __device__ __forceinline__ void wave_tile_wide(const JobDesc& job, int X0, int Y
     constexpr int NPL = decltype(nplc)::value;
     constexpr int PAR = decltype(parc)::value;
     constexpr uint32_t MOFF = PAR * SPAN, DOFF = (2 + PAR) * SPAN;
-    typename PT::V4 ring[NT][NPL];
+    typename PT::RV4 ring[NT][NPL];
     constexpr bool GPF = NPL == 4;  // table gathers run one step ahead
     // entry addresses of one step (read one step ahead) and the gathered
     // entries of two steps (the gathers of step s + 1 are issued during step s)
@@ -472,8 +474,8 @@ __device__ __forceinline__ void wave_tile_wide(const JobDesc& job, int X0, int Y
       }
 #pragma unroll
       for (int pi = 0; pi < NPL; ++pi) {
-        typename PT::V4 v;
-        for (int i = 0; i < 4; ++i) v[i] = (E)racc[pi][i];
+        typename PT::RV4 v;
+        for (int i = 0; i < 4; ++i) v[i] = (RE)racc[pi][i];
         ring[s % NT][pi] = v;
       }
       // ---- column pass + demodulation of output tile j = s - NT + 1
@@ -485,12 +487,12 @@ __device__ __forceinline__ void wave_tile_wide(const JobDesc& job, int X0, int Y
           f32x4 acc = {0.f, 0.f, 0.f, 0.f};
           static_for<0, KS>([&](auto kc) {
             constexpr int ks = decltype(kc)::value;
-            typename PT::V4 lo = ring[(j + 2 * ks) % NT][pi];
-            typename PT::V4 hi;
+            typename PT::RV4 lo = ring[(j + 2 * ks) % NT][pi];
+            typename PT::RV4 hi;
             if constexpr (2 * ks + 1 < NT) hi = ring[(j + 2 * ks + 1) % NT][pi];
-            else hi = typename PT::V4{(E)0.f, (E)0.f, (E)0.f, (E)0.f};
-            typename PT::V8 a = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
-            acc = PT::mma(a, bcol[ks], acc);
+            else hi = typename PT::RV4{(RE)0.f, (RE)0.f, (RE)0.f, (RE)0.f};
+            typename PT::RV8 a = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+            acc = PT::mma_col(a, bcol[ks], acc);
           });
           for (int i = 0; i < 4; ++i) fb[pi][i] = acc[i];
         }
@@ -581,7 +583,7 @@ template <int PREC, int NT, int TH, bool WIDE>
 constexpr bool kLayoutBuildable = WIDE ? kWideBuildable<PREC, NT, TH> : kWaveBuildable<PREC, NT, TH>;
 
 template <int PREC, int NT, int TH, bool WIDE>
-__global__ void __launch_bounds__(kWaveThreads) BF_WAVE_OCC wave_kernel(const JobDesc job) {
+__global__ void __launch_bounds__(kWaveThreads) wave_kernel(const JobDesc job) {
   if constexpr (kLayoutBuildable<PREC, NT, TH, WIDE>) {
     using Off = std::conditional_t<WIDE, uint32_t, uint16_t>;
     constexpr size_t TILE_ELEMS = WIDE ? (size_t)WideLds<PREC, NT, TH>::FROWS * WideLds<PREC, NT, TH>::FW
@@ -597,7 +599,7 @@ __global__ void __launch_bounds__(kWaveThreads) BF_WAVE_OCC wave_kernel(const Jo
 // cost-ordered list; item = (job index, tile x0, tile y0, -).  Dynamic LDS is
 // sized for T_max: cos/sin table first, then the per-harmonic tables.
 template <int PREC, int NT, int TH, bool WIDE>
-__global__ void __launch_bounds__(kWaveThreads) BF_WAVE_OCC wave_batched_kernel(const JobDesc* __restrict__ jobs,
+__global__ void __launch_bounds__(kWaveThreads) wave_batched_kernel(const JobDesc* __restrict__ jobs,
                                                                     const int4* __restrict__ items,
                                                                     int n_items, int t_max) {
   if constexpr (kLayoutBuildable<PREC, NT, TH, WIDE>) {
@@ -622,22 +624,16 @@ bool wave_fits(int T, int F) {
   return kWaveBuildable<PREC, NT, TH> && WaveLds<PREC, NT, TH>::total + wave_dynamic_lds(T, F) <= kLdsLimit;
 }
 
-// the wide layout: gray levels 0..255 (F <= 255) and the larger tile in LDS;
-// BF_WAVE_NARROW=1 in the environment forces the 16-bit-offset layout
-inline bool wide_allowed() {
-  const char* e = getenv("BF_WAVE_NARROW");
-  return !(e && e[0] == '1');
-}
+// the wide layout: gray levels 0..255 (F <= 255) and the larger tile in LDS
 template <int PREC, int NT, int TH>
 bool wide_fits(int T, int F) {
-  return kWideBuildable<PREC, NT, TH> && F <= 255 && wide_allowed() &&
-         WideLds<PREC, NT, TH>::total + wide_dynamic_lds(T) <= kLdsLimit;
+  return kWideBuildable<PREC, NT, TH> && F <= 255 && WideLds<PREC, NT, TH>::total + wide_dynamic_lds(T) <= kLdsLimit;
 }
 
 template <int PREC, int NT, int TH>
 hipError_t launch_wave(const JobDesc& job, hipStream_t stream) {
   dim3 grid((job.width + kWaveCols - 1) / kWaveCols, (job.height + TH - 1) / TH);
-  if (wide_fits<PREC, NT, TH>(job.T, job.F))
+  if (!(job.flags & BF_FLAG_OFFSETS16) && wide_fits<PREC, NT, TH>(job.T, job.F))
     hipLaunchKernelGGL((wave_kernel<PREC, NT, TH, true>), grid, dim3(kWaveThreads), wide_dynamic_lds(job.T), stream,
                        job);
   else
@@ -678,21 +674,22 @@ hipError_t with_wave_rows(int th, F&& fn) {
 template <int PREC, int NT>
 TileChoice choose_tile(const JobDesc& job, int th_pref) {
   const bool integer = (job.flags & BF_FLAG_INTEGER_INPUT) != 0;
+  const bool o16 = (job.flags & BF_FLAG_OFFSETS16) != 0;
   if constexpr (PREC != BF_PLANES_FP32) {
     if (integer) {
-      if (th_pref >= 144 && wave_ok<PREC, NT, 144>(job.T, job.F)) return TileChoice{kWaveCols, 144, 1};
-      if (th_pref >= 128 && wave_ok<PREC, NT, 128>(job.T, job.F)) return TileChoice{kWaveCols, 128, 1};
-      if (th_pref >= 96 && wave_ok<PREC, NT, 96>(job.T, job.F)) return TileChoice{kWaveCols, 96, 1};
-      if (th_pref >= 64 && wave_ok<PREC, NT, 64>(job.T, job.F)) return TileChoice{kWaveCols, 64, 1};
-      if (wave_ok<PREC, NT, 32>(job.T, job.F)) return TileChoice{kWaveCols, 32, 1};
+      if (th_pref >= 144 && wave_ok<PREC, NT, 144>(job.T, job.F)) return TileChoice{kWaveCols, 144, 1, o16};
+      if (th_pref >= 128 && wave_ok<PREC, NT, 128>(job.T, job.F)) return TileChoice{kWaveCols, 128, 1, o16};
+      if (th_pref >= 96 && wave_ok<PREC, NT, 96>(job.T, job.F)) return TileChoice{kWaveCols, 96, 1, o16};
+      if (th_pref >= 64 && wave_ok<PREC, NT, 64>(job.T, job.F)) return TileChoice{kWaveCols, 64, 1, o16};
+      if (wave_ok<PREC, NT, 32>(job.T, job.F)) return TileChoice{kWaveCols, 32, 1, o16};
     }
   } else if (integer) {
-    if (th_pref >= 128 && staged_fits<PREC, NT, 128>(job.T, job.F)) return TileChoice{Geo<PREC, NT>::COLS, 128, 2};
-    if (th_pref >= 96 && staged_fits<PREC, NT, 96>(job.T, job.F)) return TileChoice{Geo<PREC, NT>::COLS, 96, 2};
-    if (th_pref >= 64 && staged_fits<PREC, NT, 64>(job.T, job.F)) return TileChoice{Geo<PREC, NT>::COLS, 64, 2};
-    if (staged_fits<PREC, NT, 32>(job.T, job.F)) return TileChoice{Geo<PREC, NT>::COLS, 32, 2};
+    if (th_pref >= 128 && staged_fits<PREC, NT, 128>(job.T, job.F)) return TileChoice{Geo<PREC, NT>::COLS, 128, 2, false};
+    if (th_pref >= 96 && staged_fits<PREC, NT, 96>(job.T, job.F)) return TileChoice{Geo<PREC, NT>::COLS, 96, 2, false};
+    if (th_pref >= 64 && staged_fits<PREC, NT, 64>(job.T, job.F)) return TileChoice{Geo<PREC, NT>::COLS, 64, 2, false};
+    if (staged_fits<PREC, NT, 32>(job.T, job.F)) return TileChoice{Geo<PREC, NT>::COLS, 32, 2, false};
   }
-  return TileChoice{Geo<PREC, NT>::COLS, 32, 0};
+  return TileChoice{Geo<PREC, NT>::COLS, 32, 0, false};
 }
 
 // One persistent launch over `n_items` items of one (family, TH) class.
@@ -725,7 +722,7 @@ hipError_t launch_batched_class(const JobDesc* jobs, const int4* items, int n_it
                              jobs, items, n_items, t_max);
           return hipGetLastError();
         };
-        if (wide_fits<PREC, NT, TH>(t_max, f_max)) return go(std::true_type{}, wide_dynamic_lds(t_max));
+        if (!tc.offsets16 && wide_fits<PREC, NT, TH>(t_max, f_max)) return go(std::true_type{}, wide_dynamic_lds(t_max));
         return go(std::false_type{}, wave_dynamic_lds(t_max, f_max));
       });
     }

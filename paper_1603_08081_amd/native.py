@@ -29,6 +29,7 @@ RANGE = {"gaussian": 0, "exponential": 1, "table": 2}
 SPATIAL = {"gaussian": 0, "box": 1}
 PLANES = {"fp32": 0, "fp16": 1, "bf16": 2}
 BF_FLAG_INTEGER_INPUT = 1
+BF_FLAG_OFFSETS16 = 2
 
 
 class BfError(RuntimeError):
@@ -157,7 +158,8 @@ class Job:
 
     def __init__(self, src, dst, *, spatial="gaussian", sigma_s=1.0, W=-1, range_kind="gaussian",
                  sigma_r=30.0, T=255, eps=1e-2, K_max=None, d=None, phi_table=None,
-                 integer_input=False, f_max=0, height=None, width=None, src_pitch=None, dst_pitch=None):
+                 integer_input=False, f_max=0, height=None, width=None, src_pitch=None, dst_pitch=None,
+                 offsets16=False):
         self._keep = []
         s = bf_job()
         s.src = _ptr(src)
@@ -183,7 +185,7 @@ class Job:
             self._keep.append(dd)
             s.d = dd.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             s.K = len(dd) - 1
-        s.flags = BF_FLAG_INTEGER_INPUT if integer_input else 0
+        s.flags = (BF_FLAG_INTEGER_INPUT if integer_input else 0) | (BF_FLAG_OFFSETS16 if offsets16 else 0)
         s.f_max = int(f_max)
         self.struct = s
 

@@ -20,10 +20,11 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 def test_algorithmic_flops_gaussian_and_box():
-    # K = 32, W = 24: 129 planes, two passes of 49 MACs
-    assert bench.alg_flops_per_px(32, 24) == 129 * 2 * 49 * 2 == 25284
+    # K = 32, W = 24: 129 planes, two passes of 49 MACs, plus 16 flops per
+    # harmonic of modulation and demodulation
+    assert bench.alg_flops_per_px(32, 24) == 129 * 2 * 49 * 2 + 16 * 32 == 25796
     # a box filter's passes are running sums: one add and one subtract each
-    assert bench.alg_flops_per_px(24, 15, "box") == 97 * 2 * 2
+    assert bench.alg_flops_per_px(24, 15, "box") == 97 * 2 * 2 + 16 * 24
     assert bench.alg_flops_per_px(24, 15, "box") < bench.alg_flops_per_px(24, 15)
 
 

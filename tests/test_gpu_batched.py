@@ -64,12 +64,12 @@ def _inputs(specs):
     return imgs
 
 
-def _jobs(native, specs, srcs, dsts):
+def _jobs(native, specs, srcs, dsts, offsets16=False):
     out = []
     for s, x, y in zip(specs, srcs, dsts):
         out.append(native.Job(x, y, spatial=s["spatial"], sigma_s=s["sigma_s"], W=s["W"], range_kind=s["rk"],
                               sigma_r=s["sr"], T=s["T"], eps=s["eps"], K_max=s.get("K_max", min(40, s["T"])),
-                              integer_input=s["integer"]))
+                              integer_input=s["integer"], offsets16=offsets16))
     return out
 
 
@@ -125,10 +125,11 @@ def test_grid_modes_agree(prec, grid, monkeypatch):
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
-def test_offset_layouts_agree(prec, monkeypatch):
+def test_offset_layouts_agree(prec):
     """The 16-bit wave kernel stages gray-level table offsets either as 16-bit
-    offsets or as 32-bit LDS addresses (gray levels 0..255, tile fits LDS);
-    both layouts compute the same bits, through bf_filter and batched."""
+    offsets (BF_FLAG_OFFSETS16) or as 32-bit LDS addresses (gray levels
+    0..255, tile fits LDS); both layouts compute the same bits, through
+    bf_filter and batched."""
     torch = _torch()
     from paper_1603_08081_amd import native
     specs = _mixed_specs()
@@ -136,18 +137,17 @@ def test_offset_layouts_agree(prec, monkeypatch):
     srcs = [torch.from_numpy(f).cuda() for f in imgs]
     stream = torch.cuda.current_stream()
     outs = {}
-    for narrow in ("0", "1"):
-        monkeypatch.setenv("BF_WAVE_NARROW", narrow)
+    for narrow in (False, True):
         single = [torch.full_like(x, -1.0) for x in srcs]
-        for j in _jobs(native, specs, srcs, single):
+        for j in _jobs(native, specs, srcs, single, offsets16=narrow):
             native.bf_filter(j, prec, stream=stream)
         batched = [torch.full_like(x, -1.0) for x in srcs]
-        ws, _ = _batched(native, torch, _jobs(native, specs, srcs, batched), prec, stream)
+        ws, _ = _batched(native, torch, _jobs(native, specs, srcs, batched, offsets16=narrow), prec, stream)
         torch.cuda.synchronize()
         outs[narrow] = (single, batched)
     for i in range(len(specs)):
         for k in range(2):
-            a, b = outs["0"][k][i], outs["1"][k][i]
+            a, b = outs[False][k][i], outs[True][k][i]
             assert torch.isfinite(a).all()
             assert torch.equal(a, b), "job %d %s" % (i, ("single", "batched")[k])
 
