@@ -202,6 +202,28 @@ int bf_filter_batched(const bf_job* jobs, int n_jobs, bf_planes prec,
                       void* workspace, size_t ws_bytes, void* hip_stream);
 
 /*
+ * bf_filter_batched_noalloc -- bf_filter_batched for callers that cannot
+ * allocate memory (code under HIP stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same jobs, kernels and results, but
+ * the job table and tile list go into a fixed device array of the library
+ * (BF_NOALLOC_SCRATCH_BYTES on each GPU, held until the process ends)
+ * instead of a caller workspace.  Nothing is allocated: no device, pinned or
+ * managed memory, no staging buffer.  The table is copied from ordinary host
+ * memory with hipMemcpyAsync on `hip_stream`, then the class launches follow
+ * on the same stream.  The caller still owns src and dst.
+ *   Limit: the table (bf_workspace_bytes() of the same jobs) must fit
+ *   BF_NOALLOC_SCRATCH_BYTES, else BF_E_UNSUPPORTED and nothing is enqueued.
+ *   Every call on one GPU uses that GPU's single array: calls that overlap in
+ *   time on one GPU (several host threads, or several streams whose work
+ *   overlaps) race on it and must not be made; calls in one stream order are
+ *   safe.  The array keeps the last call's table, which the next call
+ *   overwrites whole before its kernels read it.
+ * Returns as bf_filter_batched.
+ */
+#define BF_NOALLOC_SCRATCH_BYTES (4u << 20)
+int bf_filter_batched_noalloc(const bf_job* jobs, int n_jobs, bf_planes prec, void* hip_stream);
+
+/*
  * Plans: bf_filter_batched split into its host part (done once) and its
  * device part (repeated), for callers that filter the same buffers again and
  * again (video frames written into the same src buffers, serving loops).

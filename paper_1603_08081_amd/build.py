@@ -36,6 +36,7 @@ def _units():
         units.append((os.path.join(CSRC, s), os.path.join(BUILD, s.replace(".cpp", ".o")), []))
     units.append((os.path.join(CSRC, "bf_range.hip"), os.path.join(BUILD, "bf_range.o"), []))
     units.append((os.path.join(CSRC, "bf_recursive.hip"), os.path.join(BUILD, "bf_recursive.o"), []))
+    units.append((os.path.join(CSRC, "bf_noalloc.hip"), os.path.join(BUILD, "bf_noalloc.o"), []))
     for p in PRECS:
         for nt in NTS:
             units.append((os.path.join(CSRC, "bf_fused_inst.hip"),

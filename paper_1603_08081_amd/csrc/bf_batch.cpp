@@ -486,6 +486,32 @@ extern "C" int bf_filter_batched(const bf_job* jobs, int n_jobs, bf_planes prec,
   return p.status;
 }
 
+namespace bf {
+int filter_batched_pageable(const bf_job* jobs, int n_jobs, bf_planes prec, size_t table_cap, const char* cap_name,
+                            int (*table_of)(hipStream_t, void**), hipStream_t stream) {
+  PlanData p;
+  int rc = build_plan(jobs, n_jobs, prec, p);
+  if (rc < 0) return rc;
+  if (p.ws_bytes > table_cap)
+    return fail(BF_E_UNSUPPORTED, "the job table and tiles need " + std::to_string(p.ws_bytes) +
+                                      " bytes, more than " + cap_name + " = " + std::to_string(table_cap));
+  void* table_dev = nullptr;
+  rc = table_of(stream, &table_dev);
+  if (rc != BF_OK) return rc;
+  // the table in ordinary host memory; a copy from pageable memory has been
+  // read out of it by the time hipMemcpyAsync returns
+  std::vector<unsigned char> host(p.items_off + sizeof(int4) * p.items.size(), 0);
+  std::memcpy(host.data(), p.descs.data(), sizeof(JobDesc) * p.descs.size());
+  std::memcpy(host.data() + p.items_off, p.items.data(), sizeof(int4) * p.items.size());
+  hipError_t e = hipMemcpyAsync(table_dev, host.data(), host.size(), hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return fail(BF_E_DEVICE, std::string("job table copy failed: ") + hipGetErrorString(e));
+  rc = launch_all(p, table_dev, stream);
+  if (rc < 0) return rc;
+  if (p.status != BF_OK) set_error("a fit stopped at K_max with ||b - A d|| > eps");
+  return p.status;
+}
+}  // namespace bf
+
 extern "C" int bf_plan_create(const bf_job* jobs, int n_jobs, bf_planes prec, bf_plan** plan) {
   if (!plan) return fail(BF_E_INVALID, "plan must be non-NULL");
   *plan = nullptr;

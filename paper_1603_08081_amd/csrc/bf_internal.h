@@ -65,6 +65,15 @@ TileChoice choose_tile(const JobDesc& job, bf_planes prec, int th_pref);
 hipError_t launch_batched(const JobDesc* jobs_dev, const int4* items_dev, int n_items, int t_max, int f_max,
                           bf_planes prec, int window_tiles, TileChoice tc, int grid, hipStream_t stream);
 
+// bf_filter_batched with the job table and tiles copied straight from
+// ordinary host memory into device memory of table_cap bytes (256-byte
+// aligned; table_of(stream, &ptr) returns its address on the stream's device
+// and is called only after every argument and the table size have been
+// checked): no pinned staging and no allocation of device or pinned memory.
+// BF_E_UNSUPPORTED (naming cap_name) when the table does not fit.
+int filter_batched_pageable(const bf_job* jobs, int n_jobs, bf_planes prec, size_t table_cap, const char* cap_name,
+                            int (*table_of)(hipStream_t, void**), hipStream_t stream);
+
 // thread-local error text
 void set_error(const std::string& msg);
 // set_error(msg) and return code

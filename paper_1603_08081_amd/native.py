@@ -24,6 +24,7 @@ BF_E_UNSUPPORTED = -5
 BF_MAX_T = 1024
 BF_MAX_K = 255
 BF_MAX_W = 64
+BF_NOALLOC_SCRATCH_BYTES = 4 << 20
 
 RANGE = {"gaussian": 0, "exponential": 1, "table": 2}
 SPATIAL = {"gaussian": 0, "box": 1}
@@ -86,6 +87,8 @@ def _load():
     lib.bf_filter.restype = I
     lib.bf_filter_batched.argtypes = [jp, I, I, P, Z, P]
     lib.bf_filter_batched.restype = I
+    lib.bf_filter_batched_noalloc.argtypes = [jp, I, I, P]
+    lib.bf_filter_batched_noalloc.restype = I
     lib.bf_plan_create.argtypes = [jp, I, I, ctypes.POINTER(P)]
     lib.bf_plan_create.restype = I
     lib.bf_plan_workspace_bytes.argtypes = [P]
@@ -235,6 +238,11 @@ def bf_filter_batched(jobs: Sequence[Job], prec: str = "fp32", workspace=None, w
     arr = (bf_job * len(jobs))(*[j.struct for j in jobs])
     return _check(lib.bf_filter_batched(arr, len(jobs), PLANES[prec], _ptr(workspace), int(ws_bytes),
                                         _stream_handle(stream)))
+
+
+def bf_filter_batched_noalloc(jobs: Sequence[Job], prec: str = "fp32", stream=None) -> int:
+    arr = (bf_job * len(jobs))(*[j.struct for j in jobs])
+    return _check(lib.bf_filter_batched_noalloc(arr, len(jobs), PLANES[prec], _stream_handle(stream)))
 
 
 class Plan:

@@ -313,3 +313,18 @@ def test_recursive_filter_workspace_checks():
         with pytest.raises(native.BfError) as ei:
             native.bf_filter_recursive(j, ptr, n, stream=0)
         assert ei.value.code == native.BF_E_WORKSPACE
+
+
+def test_noalloc_batched_refuses_oversized_tables_before_device_work():
+    # 1700 descriptors exceed the library's fixed table array; the refusal
+    # comes from the host-side plan, before any HIP call
+    jobs = [_job(height=32, width=32, dst=FAKE_DST + i * 4096) for i in range(1700)]
+    assert native.bf_workspace_bytes(jobs, "fp16") > native.BF_NOALLOC_SCRATCH_BYTES
+    with pytest.raises(native.BfError) as ei:
+        native.bf_filter_batched_noalloc(jobs, "fp16", stream=0)
+    assert ei.value.code == native.BF_E_UNSUPPORTED
+    assert "BF_NOALLOC_SCRATCH_BYTES" in native.bf_last_error()
+    # argument errors are reported as by bf_filter_batched
+    with pytest.raises(native.BfError) as ei:
+        native.bf_filter_batched_noalloc([_job(), _job(height=0)], "fp16", stream=0)
+    assert ei.value.code == native.BF_E_INVALID
