@@ -32,6 +32,7 @@ METRIC = "Mpix/s, FP32 vs BF16-plane batched, at max err <0.5 gray level; % HBM 
 PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}   # dense MFMA, MI355X published
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # 256 CUs x 2.4 GHz x 256 flop per clock (packed FMA)
+PEAK_FP64_VECTOR_TFLOPS = 78.6    # 256 CUs x 2.4 GHz x 128 flop per clock
 
 
 def log(msg):
@@ -193,9 +194,6 @@ def run_sweep(args):
         print(json.dumps(line), flush=True)
 
 
-PEAK_FP64_VECTOR_TFLOPS = 78.6
-
-
 def recursive_flops_per_px(K):
     """Recursions of the recursive-Gaussian path: per harmonic, four planes,
     two axes, a causal and an anti-causal fourth-order recursion of 8
@@ -207,10 +205,10 @@ def recursive_bytes_per_px(K):
     """Bytes per pixel the recursive-Gaussian path moves to and from memory
     (before caches), per harmonic: the row pass reads f in both directions and
     writes, re-reads and rewrites four float32 planes (56); the column pass
-    reads them in both directions, writes and re-reads its causal parts,
-    reads f and writes two float32 shares (76); the final sum reads the
-    shares (8).  Plus the output."""
-    return (K + 1) * (56 + 76 + 8) + 4
+    reads them and f in both directions, writes two float32 shares on the way
+    down and reads and rewrites them on the way up (64); the final sum reads
+    the shares (8).  Plus the output."""
+    return (K + 1) * (56 + 64 + 8) + 4
 
 
 def run_recursive(args):
@@ -219,7 +217,9 @@ def run_recursive(args):
     import paper_1603_08081_amd as bfm  # noqa: F401
     from paper_1603_08081_amd import native
     from synth import WORKLOADS, workload_images
-    wl = WORKLOADS[args.workload]
+    wl = dict(WORKLOADS[args.workload])
+    if args.sigma_s:
+        wl["sigma_s"] = args.sigma_s
     img = workload_images(args.workload, limit=1)[0]
     H, Wd = img.shape
     src = torch.from_numpy(np.ascontiguousarray(img, dtype=np.float32)).cuda()
@@ -297,6 +297,9 @@ def main():
     ap.add_argument("--recursive", action="store_true",
                     help="instead of the headline line: bf_filter_recursive (Deriche's recursive "
                          "Gaussian as the spatial smoothing) on one frame of the workload")
+    ap.add_argument("--sigma-s", type=float, default=None,
+                    help="--recursive: spatial sigma instead of the workload's (above 21.3 the truncated "
+                         "window W = ceil(3 sigma) exceeds the largest window of bf_filter, 64)")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the headline line: the Tables 1-3 analogues (one JSON line per setting)")
     args = ap.parse_args()
@@ -318,7 +321,7 @@ def main():
 
     import paper_1603_08081_amd as bfm  # noqa: F401
     from paper_1603_08081_amd import native
-    from synth import WORKLOADS, batch_specs, workload_images
+    from synth import WORKLOADS, batch_specs, range_table, workload_images
 
     wl = WORKLOADS[args.workload]
     t0 = time.time()
@@ -335,10 +338,11 @@ def main():
                        sigma_r=sp["sigma_r"]) for sp in batch_specs(wl["n"], wl["seed"])[:n]]
     fits = {}
     t_fit = time.time()
+    phi_table = range_table(wl["table"], wl["T"]) if "table" in wl else None
     for p in params:
         key = (p["range_kind"], p["sigma_r"])
         if key not in fits:
-            fits[key] = native.bf_fit_coeffs(key[0], key[1], wl["T"], wl["eps"], wl["K_max"])[1]
+            fits[key] = native.bf_fit_coeffs(key[0], key[1], wl["T"], wl["eps"], wl["K_max"], phi_table=phi_table)[1]
         p["d"] = fits[key]
         p["K"] = len(p["d"]) - 1
     fit_ms = (time.time() - t_fit) * 1e3 / len(fits)
@@ -432,7 +436,7 @@ def main():
         extra["fp32_value"] = round(v32, 1)
         extra["fp32_ms_per_step"] = round(ms32, 3)
         extra["speedup_vs_fp32"] = round(value / v32, 3)
-    if args.precision != "fp16" and not args.no_fp16_alongside and not uniform:
+    if args.precision != "fp16" and not args.no_fp16_alongside:
         outs["fp16"] = [torch.empty_like(x) for x in srcs]
         ms16 = timed("fp16", outs["fp16"], args.steps, 1)
         extra["fp16_value"] = round(px / (ms16 * 1e-3) / 1e6, 1)
@@ -455,18 +459,25 @@ def main():
     avg_launch_s = ms * 1e-3 / launches
     flops = alg_flops / launches   # algorithmic flops of one launch
     achieved = flops / avg_launch_s / 1e12
-    # a box filter's algorithmic work is running sums on the vector ALUs (the
-    # kernels here run it as MFMA Toeplitz products all the same), so it is
-    # priced against the fp32 vector peak
-    peak = PEAK_FP32_VECTOR_TFLOPS if all_box else PEAK_TFLOPS[args.precision]
-    fam = {1: "wave_batched_kernel", 2: "fused_batched_kernel", 0: "fused_batched_kernel (general phase)"}
+    # a box filter's algorithmic work is running sums on the vector ALUs: the
+    # float32-plane box kernel runs them in float64 (priced against the fp64
+    # vector peak); the 16-bit paths run the box as MFMA Toeplitz products
+    # all the same (priced against the fp32 vector peak)
     main_family = max(plans[args.precision]["classes"], key=lambda c: c["items"])["family"]
+    if all_box:
+        peak = PEAK_FP64_VECTOR_TFLOPS if main_family == 3 else PEAK_FP32_VECTOR_TFLOPS
+    else:
+        peak = PEAK_TFLOPS[args.precision]
+    fam = {1: "wave_batched_kernel", 2: "fused_batched_kernel", 0: "fused_batched_kernel (general phase)",
+           3: "box_batched_kernel (float64 running sums)"}
     roof = {"bound": "alu" if all_box else "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
             "traffic": (measured_traffic(args.workload, args.precision, n,
                                          plans[args.precision]["classes"][0]["tile_rows"])
                         if launches == 1 else None),
-            "kernel": fam[main_family] + " (modulate + row/column MFMA Toeplitz + demodulate + divide)",
+            "kernel": fam[main_family] + (" (modulate + row/column running sums + demodulate + divide)"
+                                          if main_family == 3 else
+                                          " (modulate + row/column MFMA Toeplitz + demodulate + divide)"),
             "alg_flops_per_px": round(alg_flops / px, 1), "launches_per_step": launches,
             "plan": plans[args.precision]["classes"]}
     if launches == 1 and main_family == 1 and uniform:
@@ -497,7 +508,7 @@ def main():
             pix = (rows[:, None] * Wd + np.arange(Wd)[None, :]).ravel()
             ref = oracle.fourier(imgs[fi], p["spatial"], p["sigma_s"], W, p["d"], wl["T"], pixels=pix)
             dire = oracle.direct(imgs[fi], p["spatial"], p["sigma_s"], W, p["range_kind"], p["sigma_r"],
-                                 T=wl["T"], pixels=pix)
+                                 T=wl["T"], table=phi_table, pixels=pix)
             for k, o in outs.items():
                 got = o[fi].cpu().numpy().ravel()[pix]
                 errs[k].append(float(np.abs(got - ref).max()))
@@ -561,7 +572,8 @@ def main():
         H, Wd = imgs[0].shape
         config = {"workload": args.workload, "frames": n, "height": H, "width": Wd,
                   "spatial": wl["spatial"], "sigma_s": wl["sigma_s"], "W": wl["W"],
-                  "range": wl["range_kind"], "sigma_r": wl["sigma_r"], "T": wl["T"], "K": params[0]["K"],
+                  "range": wl.get("table", wl["range_kind"]), "sigma_r": wl["sigma_r"], "T": wl["T"],
+                  "K": params[0]["K"],
                   "planes": args.precision, "accumulation": "fp32"}
     else:
         config = {"workload": args.workload, "images": n, "megapixels": round(px / 1e6, 2),

@@ -329,15 +329,15 @@ int bf_dynamic_range(const float* src, int height, int width, int src_pitch, int
  * result differs from bf_filter's truncated Gaussian of eq. (2) by the
  * difference of the two spatial kernels (a variant, not the same filter).
  *   job         as for bf_filter, except: spatial must be BF_SPATIAL_GAUSSIAN,
- *               0 < sigma_s <= 1024, W is not used; with
+ *               0 < sigma_s <= 256, W is not used; with
  *               BF_FLAG_INTEGER_INPUT the row pass takes cos and sin of
  *               k w f from a float32 table of pi m / T, m = k f mod 2T
  *               (same contract as for bf_filter), otherwise phases are
  *               computed per pixel in float64
  *   workspace   device memory of at least bf_recursive_workspace_bytes(job)
- *               bytes (40 (K + 1) per pixel: the row-smoothed planes and the
- *               causal column parts of every harmonic, and each harmonic's
- *               float32 shares of numerator and denominator), 256-byte
+ *               bytes (24 (K + 1) per pixel: the row-smoothed planes of every
+ *               harmonic and each harmonic's float32 shares of numerator and
+ *               denominator), 256-byte
  *               aligned, owned by the caller, not overlapping src or dst; in
  *               use until the stream has passed the launches
  *   hip_stream  stream to enqueue on: three launches, asynchronous

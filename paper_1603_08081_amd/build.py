@@ -37,6 +37,7 @@ def _units():
     units.append((os.path.join(CSRC, "bf_range.hip"), os.path.join(BUILD, "bf_range.o"), []))
     units.append((os.path.join(CSRC, "bf_recursive.hip"), os.path.join(BUILD, "bf_recursive.o"), []))
     units.append((os.path.join(CSRC, "bf_noalloc.hip"), os.path.join(BUILD, "bf_noalloc.o"), []))
+    units.append((os.path.join(CSRC, "bf_box.hip"), os.path.join(BUILD, "bf_box.o"), []))
     for p in PRECS:
         for nt in NTS:
             units.append((os.path.join(CSRC, "bf_fused_inst.hip"),

@@ -50,6 +50,7 @@ int resolve_job(const bf_job* j, Resolved* out) {
     return fail(BF_E_INVALID, "pitch must be >= width");
   if (j->spatial != BF_SPATIAL_GAUSSIAN && j->spatial != BF_SPATIAL_BOX)
     return fail(BF_E_INVALID, "unknown spatial kernel kind");
+  if (j->flags & ~(BF_FLAG_INTEGER_INPUT | BF_FLAG_OFFSETS16)) return fail(BF_E_INVALID, "unknown bits in flags");
   int W = j->W;
   if (j->spatial == BF_SPATIAL_GAUSSIAN) {
     if (!(j->sigma_s > 0.0) || !std::isfinite(j->sigma_s))
@@ -104,7 +105,7 @@ int resolve_job(const bf_job* j, Resolved* out) {
   jd.K = static_cast<int>(d.size()) - 1;
   jd.T = j->T;
   jd.F = j->f_max > 0 ? j->f_max : j->T;
-  jd.flags = j->flags;
+  jd.flags = j->flags | (j->spatial == BF_SPATIAL_BOX ? kJobBox : 0);
   // centre of the gray-level range: |f - c0| <= F / 2 before 16-bit rounding
   jd.c0 = 0.5f * static_cast<float>(jd.F);
   // unit-sum 1-D profile (eq. (2) is separable: w(x, y) = w1(x) w1(y))

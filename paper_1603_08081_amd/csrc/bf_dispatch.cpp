@@ -21,6 +21,7 @@ hipError_t launch_prec(const JobDesc& job, int th, hipStream_t stream) {
 }  // namespace
 
 hipError_t launch_fused(const JobDesc& job, bf_planes prec, int th, hipStream_t stream) {
+  if (prec == BF_PLANES_FP32 && box_supported(job)) return launch_box(job, stream);
   switch (prec) {
     case BF_PLANES_FP32: return launch_prec<BF_PLANES_FP32>(job, th, stream);
     case BF_PLANES_FP16: return launch_prec<BF_PLANES_FP16>(job, th, stream);
@@ -61,6 +62,7 @@ hipError_t batched_prec(const JobDesc* jobs, const int4* items, int n, int t_max
 }  // namespace
 
 TileChoice choose_tile(const JobDesc& job, bf_planes prec, int th_pref) {
+  if (prec == BF_PLANES_FP32 && box_supported(job)) return TileChoice{64, 64, 3, false};
   switch (prec) {
     case BF_PLANES_FP32: return choose_prec<BF_PLANES_FP32>(job, th_pref);
     case BF_PLANES_FP16: return choose_prec<BF_PLANES_FP16>(job, th_pref);
@@ -70,6 +72,7 @@ TileChoice choose_tile(const JobDesc& job, bf_planes prec, int th_pref) {
 
 hipError_t launch_batched(const JobDesc* jobs_dev, const int4* items_dev, int n_items, int t_max, int f_max,
                           bf_planes prec, int nt, TileChoice tc, int grid, hipStream_t stream) {
+  if (tc.family == 3) return launch_box_batched(jobs_dev, items_dev, n_items, t_max, f_max, grid, stream);
   switch (prec) {
     case BF_PLANES_FP32: return batched_prec<BF_PLANES_FP32>(jobs_dev, items_dev, n_items, t_max, f_max, nt, tc, grid, stream);
     case BF_PLANES_FP16: return batched_prec<BF_PLANES_FP16>(jobs_dev, items_dev, n_items, t_max, f_max, nt, tc, grid, stream);

@@ -57,9 +57,14 @@ typedef __bf16 b16x4 __attribute__((ext_vector_type(4)));
 template <int PREC>
 struct Planes;
 
+// kRefineQ: denominators (unit-sum weights) below this are re-evaluated
+// directly (see refine_pixels); the rounding error of the numerator and
+// denominator sums divided by Q is the output error, and for Q down to w(0)
+// that division amplifies it up to a few hundred times.
 template <>
 struct Planes<BF_PLANES_FP32> {
   using E = float;
+  static constexpr float kRefineQ = 0.005f;
   static __device__ __forceinline__ float round(float x) { return x; }
 };
 
@@ -81,6 +86,7 @@ struct RingF16 {
 
 template <>
 struct Planes<BF_PLANES_FP16> : RingF16 {
+  static constexpr float kRefineQ = 0.02f;
   using E = _Float16;
   using V8 = f16x8;
   using V4 = f16x4;
@@ -95,6 +101,7 @@ struct Planes<BF_PLANES_FP16> : RingF16 {
 
 template <>
 struct Planes<BF_PLANES_BF16> : RingF16 {
+  static constexpr float kRefineQ = 0.05f;
   using E = __bf16;
   using V8 = b16x8;
   using V4 = b16x4;
@@ -193,6 +200,160 @@ __device__ __forceinline__ void phase_general(float kf, float f, const PhaseTab&
   sincospif(r * pt.inv_t, &sr, &cr);
   c = v.x * cr - v.y * sr;
   s = v.y * cr + v.x * sr;
+}
+
+// ---- direct re-evaluation of ill-conditioned pixels -----------------------
+// The output is P / Q + c0, and rounding errors in P and Q (16-bit planes
+// and intermediates, or fp32 sums) reach the output divided by Q.  With a
+// unit-sum spatial kernel Q can be as small as the centre weight w(0) at a
+// pixel whose window holds no other gray level within the range kernel's
+// reach, so there the Fourier-plane sums are re-evaluated directly: eq. (9)
+// written out over the (2W+1)^2 window with phi_K tabulated on the integer
+// differences 0..F, in float64.  These pixels are rare (a few in 10^4 on
+// natural-looking images) and the kernels find them from their own Q.
+
+// phi_K(t) = sum_k d_k cos(k w t), t = 0..F, into phi (float64, LDS); lut
+// holds cos/sin(pi m / T), m = 0..2T-1.  Called by every thread.
+__device__ __forceinline__ void build_phi_table(const JobDesc& job, const float2* lut, double* phi, int nthreads) {
+  const int T2 = 2 * job.T;
+  for (int t = threadIdx.x; t <= job.F; t += nthreads) {
+    double acc = job.d[0];
+    int m = 0;
+    for (int k = 1; k <= job.K; ++k) {
+      m += t;
+      m = m >= T2 ? m % T2 : m;  // (k t) mod 2T
+      acc = fma(job.d[k], (double)lut[m].x, acc);
+    }
+    phi[t] = acc;
+  }
+}
+
+// Bit 4 j + i of the returned mask: output (j, i) of this lane lies inside
+// the image and has !(Q >= tau) (NaN included).
+template <int NJ, class Acc>
+__device__ __forceinline__ unsigned long long refine_flags(const Acc (&Q)[NJ][4], const JobDesc& job, int Y0, int x0,
+                                                           float tau) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long fl = 0;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int yy = Y0 + 16 * j + (lane & 15), xx = x0 + 4 * (lane >> 4) + i;
+      if (yy < job.height && xx < job.width && !(Q[j][i] >= (Acc)tau)) fl |= 1ull << (4 * j + i);
+    }
+  return fl;
+}
+
+// Eq. (9) evaluated directly at one output pixel by the whole wave, written
+// to dst: the pixel sits at (r, c) from the output tile's origin (X0, Y0),
+// at staged-tile row W + r and column corg + c.  Lane l takes window
+// columns l, l + 64, ...; the rows of a column are independent loads (so
+// several are in flight), summed in float64, and a butterfly sums the lanes.
+template <class Gray>
+__device__ __forceinline__ void refine_pixel(int r, int c, const JobDesc& job, int X0, int Y0, int corg,
+                                             const float* w1s, const double* phi, Gray gray) {
+  const int lane = threadIdx.x & 63;
+  const int W = job.W;
+  const double c0 = (double)job.c0;
+  const int tr = W + r, tc = corg + c;
+  const int fi = gray(tr, tc);
+  double p = 0.0, q = 0.0;
+  for (int dx = lane; dx <= 2 * W; dx += 64) {
+    double pc = 0.0, qc = 0.0;
+#pragma unroll 4
+    for (int dy = 0; dy <= 2 * W; ++dy) {
+      const int fj = gray(tr - W + dy, tc - W + dx);
+      const double wp = (double)w1s[dy] * phi[fj >= fi ? fj - fi : fi - fj];
+      qc += wp;
+      pc = fma(wp, (double)fj - c0, pc);
+    }
+    const double wx = (double)w1s[dx];
+    p = fma(wx, pc, p);
+    q = fma(wx, qc, q);
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    p += __shfl_xor(p, o);
+    q += __shfl_xor(q, o);
+  }
+  if (lane == 0) job.dst[(size_t)(Y0 + r) * job.dst_pitch + X0 + c] = (float)(p / q + c0);
+}
+
+// The same evaluation by one thread alone (the fallback for a pixel that
+// does not fit the shared list).
+template <class Gray>
+__device__ __forceinline__ void refine_pixel_alone(int r, int c, const JobDesc& job, int X0, int Y0, int corg,
+                                                   const float* w1s, const double* phi, Gray gray) {
+  const int W = job.W;
+  const double c0 = (double)job.c0;
+  const int tr = W + r, tc = corg + c;
+  const int fi = gray(tr, tc);
+  double p = 0.0, q = 0.0;
+  for (int dy = 0; dy <= 2 * W; ++dy) {
+    double pr = 0.0, qr = 0.0;
+    for (int dx = 0; dx <= 2 * W; ++dx) {
+      const int fj = gray(tr - W + dy, tc - W + dx);
+      const double wp = (double)w1s[dx] * phi[fj >= fi ? fj - fi : fi - fj];
+      qr += wp;
+      pr = fma(wp, (double)fj - c0, pr);
+    }
+    p = fma((double)w1s[dy], pr, p);
+    q = fma((double)w1s[dy], qr, q);
+  }
+  job.dst[(size_t)(Y0 + r) * job.dst_pitch + X0 + c] = (float)(p / q + c0);
+}
+
+// Re-evaluates the flagged outputs of a workgroup's tile after the tile's
+// outputs have been stored.  Called by every thread with `any` (whether it
+// holds flagged outputs) and `each(emit)`, which calls emit(r, c) for each of
+// them, (r, c) counted from the tile's output origin (X0, Y0); gray(r, c)
+// reads staged-tile coordinates, where output (r, c) sits at row W + r and
+// column corg + c.  The flagged pixels are pooled in an LDS list so that all
+// waves share them; `scratch` (LDS free at this point, 16-byte aligned)
+// holds phi_K on 0..F and the list; a pixel beyond the list's room is done
+// by its own thread alone.
+template <class Each, class Gray>
+__device__ __forceinline__ void refine_pooled(bool any, Each each, const JobDesc& job, int X0, int Y0, int corg,
+                                              const float* w1s, const float2* lut, unsigned char* scratch,
+                                              size_t scratch_bytes, int nthreads, Gray gray) {
+  // also the barrier after which every wave is done with the tables
+  if (!__syncthreads_or(any)) return;
+  const int tid = threadIdx.x, wave = tid >> 6, nwaves = nthreads >> 6;
+  double* phi = reinterpret_cast<double*>(scratch);
+  const size_t phi_bytes = (8 * (size_t)(job.F + 1) + 15) & ~(size_t)15;
+  int* cnt = reinterpret_cast<int*>(scratch + phi_bytes);
+  uint32_t* lst = reinterpret_cast<uint32_t*>(scratch + phi_bytes + 16);
+  const int cap = scratch_bytes > phi_bytes + 16 ? (int)((scratch_bytes - phi_bytes - 16) / 4) : 0;
+  build_phi_table(job, lut, phi, nthreads);
+  if (tid == 0) *cnt = 0;
+  __syncthreads();
+  each([&](int r, int c) {
+    const int idx = atomicAdd(cnt, 1);
+    if (idx < cap) lst[idx] = (uint32_t)r | ((uint32_t)c << 16);
+    else refine_pixel_alone(r, c, job, X0, Y0, corg, w1s, phi, gray);
+  });
+  __syncthreads();
+  const int n = min(*cnt, cap);
+  for (int e = wave; e < n; e += nwaves) {
+    const uint32_t v = lst[e];
+    refine_pixel((int)(v & 0xffffu), (int)(v >> 16), job, X0, Y0, corg, w1s, phi, gray);
+  }
+}
+
+// refine_pooled for the MFMA kernels' layout: bit 4 j + i of a lane's mask
+// (refine_flags) is output (16 j + n16, 16 w + 4 g + i) of lane (g, n16) of
+// wave w.
+template <int NJ, class Gray>
+__device__ __forceinline__ void refine_tile(unsigned long long fl, const JobDesc& job, int X0, int Y0, int corg,
+                                            const float* w1s, const float2* lut, unsigned char* scratch,
+                                            size_t scratch_bytes, int nthreads, Gray gray) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  refine_pooled(fl != 0, [&](auto&& emit) {
+    for (unsigned long long m = fl; m; m &= m - 1) {
+      const int b = __ffsll((long long)m) - 1;
+      emit(16 * (b >> 2) + (lane & 15), 16 * wave + 4 * (lane >> 4) + (b & 3));
+    }
+  }, job, X0, Y0, corg, w1s, lut, scratch, scratch_bytes, nthreads, gray);
 }
 
 // One output tile (COLS x TH at X0, Y0) of one image, all harmonics.  smem
@@ -545,7 +706,8 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
     else run(std::integral_constant<int, 4>{});
   }
 
-  // ---- 5. divide and store
+  // ---- 5. divide and store; then re-evaluate the ill-conditioned pixels
+  // of integer images directly (see refine_pixels)
   float* __restrict__ dst = job.dst;
   for (int j = 0; j < NJ; ++j) {
     const int yy = Y0 + 16 * j + n16;
@@ -554,6 +716,11 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
       const int xx = x0 + 4 * g + i;
       if (xx < Wd) dst[(size_t)yy * job.dst_pitch + xx] = (float)(P[j][i] / Q[j][i] + (Acc)c0);
     }
+  }
+  if constexpr (INTEGER) {
+    const unsigned long long fl = refine_flags<NJ>(Q, job, Y0, x0, PT::kRefineQ);
+    refine_tile<NJ>(fl, job, X0, Y0, Wal, w1s, lut, tab, (size_t)kTabBytes * (job.F + 1), NTHR,
+                    [&](int r, int c) { return (int)ftile[r][c] / kTabBytes; });
   }
   (void)two_t;
   (void)inv_two_t;

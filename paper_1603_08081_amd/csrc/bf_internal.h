@@ -40,6 +40,9 @@ struct JobDesc {
   double d[BF_MAX_K + 1];       // coefficients d_0..d_K
 };
 
+// internal JobDesc.flags bits (above the public BF_FLAG_* bits)
+constexpr int kJobBox = 0x100;  // box spatial kernel (w = 1 on the window)
+
 // Geometry of the fused kernel: a workgroup owns a tile_cols(prec)-column by
 // `th`-row output tile; one wave owns a 16-column strip of it.
 inline int tile_cols(bf_planes prec) { return prec == BF_PLANES_FP32 ? 64 : 128; }
@@ -50,11 +53,19 @@ inline int window_tiles(int W) {
   return nt < 2 ? 2 : nt;
 }
 
+// running-sum box kernel (bf_box.hip): float32 planes on integer images with
+// the box spatial kernel, W <= 24
+bool box_supported(const JobDesc& job);
+hipError_t launch_box(const JobDesc& job, hipStream_t stream);
+hipError_t launch_box_batched(const JobDesc* jobs, const int4* items, int n_items, int t_max, int f_max, int grid,
+                              hipStream_t stream);
+
 // launchers (bf_fused_inst.hip instantiations); return the hipError_t of the launch
 hipError_t launch_fused(const JobDesc& job, bf_planes prec, int th, hipStream_t stream);
 
 // Tile geometry and kernel family chosen for one job: family 1 = barrier-free
-// wave kernel, 2 = shared-plane kernel with staged tile, 0 = general path.
+// wave kernel, 2 = shared-plane kernel with staged tile, 3 = running-sum box
+// kernel, 0 = general path.
 struct TileChoice {
   int cols, th, family;
   bool offsets16;  // wave kernel: stage 16-bit table offsets (BF_FLAG_OFFSETS16 on a job of the class)

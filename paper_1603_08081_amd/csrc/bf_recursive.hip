@@ -10,7 +10,9 @@
 //   2. columns: one lane per (image column, k) runs the same recursions down
 //               the row-smoothed planes and demodulates with d_k: harmonic k's
 //               share of the numerator, cos S(f cos) + sin S(f sin), and of
-//               the denominator, cos S(cos) + sin S(sin), times d_k;
+//               the denominator, cos S(cos) + sin S(sin), times d_k (the
+//               causal and anti-causal halves of S demodulated one after the
+//               other into the same shares);
 //   3. one lane per pixel sums the K + 1 shares in float64 and divides.
 // The recursions' state is float64; the phases are float64, except in the
 // row pass of integer images, which looks cos and sin of pi m / T up in a
@@ -33,7 +35,9 @@ namespace bf {
 namespace {
 
 constexpr int kLineThreads = 64;     // one wavefront of lines per workgroup
-constexpr double kMaxSigmaRec = 1024.0;
+// Above this the poles of the fourth-order recursion come so close to 1 that
+// its float64 rounding reaches 1e-5 of the signal per pass.
+constexpr double kMaxSigmaRec = 256.0;
 
 struct RecCoef {
   double nc[4];   // causal numerator, x(i) .. x(i - 3)
@@ -51,7 +55,6 @@ struct RecArgs {
   int integer;     // BF_FLAG_INTEGER_INPUT: phases of the row pass from a table
   RecCoef c;
   float* rows;     // [K + 1][4][height][width], row-smoothed planes
-  float* causal;   // [K + 1][4][height][width], causal parts of the column pass
   float* P;        // [K + 1][height][width], numerator shares
   float* Q;        // [K + 1][height][width], denominator shares
   double d[BF_MAX_K + 1];   // d_0..d_K
@@ -275,6 +278,10 @@ __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a)
   }
 }
 
+// The column pass demodulates the causal and the anti-causal halves of each
+// smoothed plane separately (demodulation is linear): the causal sweep writes
+// harmonic k's shares of numerator and denominator from its half, and the
+// anti-causal sweep adds its own, so no causal half is stored.
 __global__ void __launch_bounds__(kLineThreads) rec_cols_kernel(const RecArgs a) {
   const int x0 = blockIdx.x * kLineThreads + threadIdx.x;
   const int k = blockIdx.y;
@@ -282,12 +289,12 @@ __global__ void __launch_bounds__(kLineThreads) rec_cols_kernel(const RecArgs a)
   const int L = a.height, M = a.c.margin, Wd = a.width;
   const size_t plane = (size_t)a.height * a.width;
   const float* in = a.rows + 4 * plane * k + x0;
-  float* cz = a.causal + 4 * plane * k + x0;
   const double dk = a.d[k];
   double xh[4][4] = {};
   double yh[4][4] = {};
   for (int i = -M; i < L; ++i) {
     const size_t r = (size_t)fold(i, L) * Wd;
+    double S[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       xh[p][3] = xh[p][2];
@@ -300,7 +307,15 @@ __global__ void __launch_bounds__(kLineThreads) rec_cols_kernel(const RecArgs a)
       yh[p][2] = yh[p][1];
       yh[p][1] = yh[p][0];
       yh[p][0] = v;
-      if (i >= 0) cz[p * plane + r] = static_cast<float>(v);
+      S[p] = v;
+    }
+    if (i >= 0) {
+      const float f = a.src[(size_t)i * a.src_pitch + x0];
+      double c, s;
+      phase(f, k, a.T, &c, &s);
+      const size_t o = plane * k + (size_t)i * Wd + x0;
+      a.P[o] = static_cast<float>(dk * (c * S[0] + s * S[1]));
+      a.Q[o] = static_cast<float>(dk * (c * S[2] + s * S[3]));
     }
   }
   double xa[4][4] = {};
@@ -323,13 +338,12 @@ __global__ void __launch_bounds__(kLineThreads) rec_cols_kernel(const RecArgs a)
       S[p] = v;
     }
     if (i < L) {
-      for (int p = 0; p < 4; ++p) S[p] += cz[p * plane + r];
       const float f = a.src[(size_t)i * a.src_pitch + x0];
       double c, s;
       phase(f, k, a.T, &c, &s);
       const size_t o = plane * k + (size_t)i * Wd + x0;
-      a.P[o] = static_cast<float>(dk * (c * S[0] + s * S[1]));
-      a.Q[o] = static_cast<float>(dk * (c * S[2] + s * S[3]));
+      a.P[o] = static_cast<float>((double)a.P[o] + dk * (c * S[0] + s * S[1]));
+      a.Q[o] = static_cast<float>((double)a.Q[o] + dk * (c * S[2] + s * S[3]));
     }
   }
 }
@@ -349,10 +363,10 @@ __global__ void __launch_bounds__(256) rec_sum_kernel(const RecArgs a) {
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-// layout: rows planes, causal planes, numerator shares, denominator shares
+// layout: row-smoothed planes, numerator shares, denominator shares
 size_t rec_ws_bytes(int height, int width, int K) {
   const size_t n = (size_t)height * width, h = (size_t)K + 1;
-  return 2 * align256(4 * h * n * sizeof(float)) + 2 * align256(h * n * sizeof(float));
+  return align256(4 * h * n * sizeof(float)) + 2 * align256(h * n * sizeof(float));
 }
 
 }  // namespace
@@ -368,7 +382,7 @@ int resolve_recursive(const bf_job* job, Resolved* r) {
     return fail(BF_E_INVALID, "the recursive path smooths with a Gaussian: spatial must be BF_SPATIAL_GAUSSIAN");
   if (!(job->sigma_s > 0.0) || !std::isfinite(job->sigma_s))
     return fail(BF_E_INVALID, "sigma_s must be finite and > 0");
-  if (job->sigma_s > kMaxSigmaRec) return fail(BF_E_UNSUPPORTED, "sigma_s exceeds 1024");
+  if (job->sigma_s > kMaxSigmaRec) return fail(BF_E_UNSUPPORTED, "sigma_s exceeds 256");
   // validation and fit shared with bf_filter; the window does not apply here
   bf_job j = *job;
   j.W = 0;
@@ -407,9 +421,8 @@ extern "C" int bf_filter_recursive(const bf_job* job, void* workspace, size_t ws
   a.K = K;
   const size_t planes = align256(4 * h * n * sizeof(float)), shares = align256(h * n * sizeof(float));
   a.rows = reinterpret_cast<float*>(w);
-  a.causal = reinterpret_cast<float*>(w + planes);
-  a.P = reinterpret_cast<float*>(w + 2 * planes);
-  a.Q = reinterpret_cast<float*>(w + 2 * planes + shares);
+  a.P = reinterpret_cast<float*>(w + planes);
+  a.Q = reinterpret_cast<float*>(w + planes + shares);
   for (int k = 0; k <= K; ++k) a.d[k] = r.desc.d[k];
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
   const dim3 grows((job->height + kLineThreads - 1) / kLineThreads, K + 1);

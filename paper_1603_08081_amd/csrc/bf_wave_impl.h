@@ -314,6 +314,10 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
       if (xx < Wd) dst[(size_t)yy * job.dst_pitch + xx] = P[j][i] / Q[j][i] + c0;
     }
   }
+  // re-evaluate ill-conditioned pixels directly (see refine_tile)
+  const unsigned long long fl = refine_flags<NJ>(Q, job, Y0, x0, PT::kRefineQ);
+  refine_tile<NJ>(fl, job, X0, Y0, Wal, w1s, lut, tab, 4 * span, kWaveThreads,
+                  [&](int r, int c) { return (int)ftile[r][c] / MODB; });
   __syncthreads();  // the LDS of this tile may be reused by the caller
 }
 
@@ -554,6 +558,10 @@ __device__ __forceinline__ void wave_tile_wide(const JobDesc& job, int X0, int Y
       if (xx < Wd) dst[(size_t)yy * job.dst_pitch + xx] = P[j][i] / Q[j][i] + c0;
     }
   }
+  // re-evaluate ill-conditioned pixels directly (see refine_tile)
+  const unsigned long long fl = refine_flags<NJ>(Q, job, Y0, x0, PT::kRefineQ);
+  refine_tile<NJ>(fl, job, X0, Y0, Wal, w1s, lut, tab, 4 * (size_t)kWideSpan, kWaveThreads,
+                  [&](int r, int c) { return (int)((ftile[r][c] - tb) >> 3); });
   __syncthreads();  // the LDS of this tile may be reused by the caller
 }
 

@@ -12,4 +12,5 @@ from .images import (  # noqa: F401
     batch_specs,
     WORKLOADS,
     workload_images,
+    range_table,
 )

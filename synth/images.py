@@ -125,6 +125,22 @@ WORKLOADS: Dict[str, Dict] = {
     "gauss_8192": dict(n=1, height=8192, width=8192, seed=303, gradient=False,
                        spatial="gaussian", sigma_s=10.0, W=30,
                        range_kind="gaussian", sigma_r=10.0, T=255, eps=0.0, K_max=40),
+    # the exponential kernel at the number of harmonics where eq. (9) comes
+    # within half a gray level of eq. (1) on this image (its kink at t = 0
+    # makes the cosine series converge slowly)
+    "exp_2048_k128": dict(n=1, height=2048, width=2048, seed=202, gradient=False,
+                          spatial="gaussian", sigma_s=5.0, W=15,
+                          range_kind="exponential", sigma_r=20.0, T=255, eps=0.0, K_max=128),
+    "exp_2048_box_k160": dict(n=1, height=2048, width=2048, seed=202, gradient=False,
+                              spatial="box", sigma_s=0.0, W=15,
+                              range_kind="exponential", sigma_r=20.0, T=255, eps=0.0, K_max=160),
+    # range kernels given only by samples phi(0..T) (see range_table)
+    "tukey_2048": dict(n=1, height=2048, width=2048, seed=202, gradient=False,
+                       spatial="gaussian", sigma_s=5.0, W=15,
+                       range_kind="table", table="tukey", sigma_r=0.0, T=255, eps=1e-3, K_max=128),
+    "cauchy_2048": dict(n=1, height=2048, width=2048, seed=202, gradient=False,
+                        spatial="gaussian", sigma_s=5.0, W=15,
+                        range_kind="table", table="cauchy", sigma_r=0.0, T=255, eps=1e-3, K_max=128),
     "batch64_mixed": dict(n=64, seed=404, T=255, eps=1e-2, K_max=40, spatial="gaussian"),
     "frames32_2160x3840": dict(n=32, height=2160, width=3840, seed=50500, gradient=True,
                                spatial="gaussian", sigma_s=8.0, W=24,
@@ -144,3 +160,17 @@ def workload_images(name: str, limit: int | None = None) -> List[np.ndarray]:
     if wl["n"] == 1:
         return [polygon_image(wl["height"], wl["width"], wl["seed"], wl["gradient"])]
     return frames(n, wl["height"], wl["width"], wl["seed"], wl["gradient"])
+
+
+def range_table(name: str, T: int = 255) -> np.ndarray:
+    """Samples phi(0..T) of the sampled range kernels used as inputs: Tukey's
+    biweight with support 40, the Cauchy (Lorentzian) kernel of scale 12, and
+    a hard window of half-width 20."""
+    t = np.arange(T + 1, dtype=np.float64)
+    if name == "tukey":
+        return np.where(t < 40.0, (1.0 - (t / 40.0) ** 2) ** 2, 0.0)
+    if name == "cauchy":
+        return 1.0 / (1.0 + (t / 12.0) ** 2)
+    if name == "window":
+        return (t <= 20).astype(np.float64)
+    raise KeyError(name)

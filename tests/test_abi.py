@@ -115,9 +115,13 @@ def _job(**kw):
     (dict(d=np.ones(300)), native.BF_E_UNSUPPORTED),
     (dict(d=np.array([1.0, np.nan])), native.BF_E_INVALID),
     (dict(dst=FAKE_SRC + 4 * 100), native.BF_E_INVALID),   # overlaps src
+    (dict(flags=0x100), native.BF_E_INVALID),               # unknown flag bits
 ])
 def test_filter_rejects_bad_jobs_before_device_work(kw, code):
+    flags = kw.pop("flags", None)
     j = _job(**kw)
+    if flags is not None:
+        j.struct.flags = flags
     with pytest.raises(native.BfError) as ei:
         native.bf_filter(j, "fp32", stream=0)
     assert ei.value.code == code
@@ -288,6 +292,7 @@ def test_batched_rejects_outputs_that_overlap_other_jobs():
     (dict(spatial="box", W=3), native.BF_E_INVALID),
     (dict(sigma_s=0.0), native.BF_E_INVALID),
     (dict(sigma_s=2000.0), native.BF_E_UNSUPPORTED),
+    (dict(sigma_s=300.0), native.BF_E_UNSUPPORTED),
     (dict(T=0), native.BF_E_INVALID),
     (dict(sigma_r=-1.0), native.BF_E_INVALID),
     (dict(d=np.ones(300)), native.BF_E_UNSUPPORTED),
@@ -304,10 +309,11 @@ def test_recursive_filter_rejects_bad_jobs_before_device_work(kw, code):
 
 
 def test_recursive_filter_workspace_checks():
-    # 40 (K + 1) bytes per pixel, each of the four regions 256-byte aligned
+    # 24 (K + 1) bytes per pixel (row-smoothed planes, numerator and
+    # denominator shares), each of the three regions 256-byte aligned
     j = _job(W=0, d=np.array([1.0, 0.5, 0.25]))
-    assert native.bf_recursive_workspace_bytes(j) == 40 * 3 * 64 * 64
-    assert native.bf_recursive_workspace_bytes(_job(W=0, d=np.array([1.0]), height=3, width=5)) == 4 * 256
+    assert native.bf_recursive_workspace_bytes(j) == 24 * 3 * 64 * 64
+    assert native.bf_recursive_workspace_bytes(_job(W=0, d=np.array([1.0]), height=3, width=5)) == 3 * 256
     ws = native.bf_recursive_workspace_bytes(j)
     for ptr, n in ((None, ws), (0x30000000, ws - 1), (0x30000004, ws)):
         with pytest.raises(native.BfError) as ei:

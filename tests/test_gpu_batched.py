@@ -330,8 +330,8 @@ def test_frames32_tuned_plan_as_benchmarked():
     """The 32-frame UHD workload in the configuration the benchmark times: one
     tuned plan over all frames, graph replay; every pixel of sampled rows
     (borders, window edges, middle, seeded random) of the first, a middle and
-    the last frame against eq. (9) in FP64: float16 planes < 0.5, float32
-    planes <= 1e-3, bfloat16 reported."""
+    the last frame against eq. (9) in FP64: float16 and bfloat16 planes < 0.5,
+    float32 planes <= 1e-3."""
     torch = _torch()
     from paper_1603_08081_amd import native
     wl = WORKLOADS["frames32_2160x3840"]
@@ -364,4 +364,4 @@ def test_frames32_tuned_plan_as_benchmarked():
             worst[prec] = max(worst[prec], float(np.abs(got - ref).max()))
         plan.destroy()
     print("frames32 tuned plan, worst sampled error vs eq. (9) FP64:", worst, flush=True)
-    assert worst["fp16"] < 0.5 and worst["fp32"] <= TOL_FP32 and worst["bf16"] < 4.0
+    assert worst["fp16"] < 0.5 and worst["fp32"] <= TOL_FP32 and worst["bf16"] < 0.5

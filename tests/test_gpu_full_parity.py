@@ -33,6 +33,14 @@ def _report(name, err):
     print("%s: max err over every pixel %.4g" % (name, err), flush=True)
 
 
+def _q_report(name, Q):
+    """Share of pixels whose eq. (9) denominator (unit-sum weights) falls
+    below the thresholds under which the kernels re-evaluate a pixel
+    directly (float32 planes 0.005, float16 0.02, bfloat16 0.05)."""
+    print("%s: min Q %.4g; share below 0.005 / 0.02 / 0.05: %.3g / %.3g / %.3g"
+          % (name, Q.min(), (Q < 0.005).mean(), (Q < 0.02).mean(), (Q < 0.05).mean()), flush=True)
+
+
 def _fit(wl):
     return oracle.fit_kernel(wl["range_kind"], wl["sigma_r"], wl["T"], wl["eps"], wl["K_max"])
 
@@ -44,7 +52,8 @@ def gauss_8192():
     r = _fit(wl)
     assert r.K == 40
     print("gauss_8192: oracle over %d px on %d threads" % (f.size, oracle.num_threads()), flush=True)
-    ref = oracle.fourier(f, "gaussian", wl["sigma_s"], wl["W"], r.d, wl["T"])
+    ref, _, Q = oracle.fourier(f, "gaussian", wl["sigma_s"], wl["W"], r.d, wl["T"], with_pq=True)
+    _q_report("gauss_8192", Q)
     return wl, f, r, ref
 
 
@@ -65,7 +74,8 @@ def frame0():
     f = workload_images("frames32_2160x3840", limit=1)[0]
     r = _fit(wl)
     assert r.K == 32
-    ref = oracle.fourier(f, "gaussian", wl["sigma_s"], wl["W"], r.d, wl["T"])
+    ref, _, Q = oracle.fourier(f, "gaussian", wl["sigma_s"], wl["W"], r.d, wl["T"], with_pq=True)
+    _q_report("frames32 frame 0", Q)
     return wl, f, r, ref
 
 

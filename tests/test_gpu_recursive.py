@@ -100,3 +100,16 @@ def test_full_frame_with_one_dimensional_structure(axis):
     want = np.broadcast_to(line, (H, Wd))
     assert st == 0
     assert np.abs(out - want).max() <= TOL
+
+
+def test_matches_eq9_with_the_direct_sum_smoothing():
+    """Against the oracle's eq. (9) built on the direct sums over h (h)
+    (``convolve_smooth``) instead of its own recursion: the GPU recursions
+    must meet the smoothing's definition, not just the same recursion."""
+    f = polygon_image(96, 120, 12).astype(np.float32)
+    fit = oracle.fit_kernel("gaussian", 25.0, 255, 1e-3)
+    out, st = _run(f, sigma_s=3.0, T=255, d=fit.d, integer_input=True)
+    want = R.fourier_recursive(f, 3.0, fit.d, 255, smooth=lambda X: R.convolve_smooth(X, 3.0))
+    err = np.abs(out - want).max()
+    print("recursive vs eq. (9) with direct-sum smoothing: %.3g" % err, flush=True)
+    assert err <= TOL

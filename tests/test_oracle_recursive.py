@@ -141,3 +141,20 @@ def test_plane_assembly_with_the_truncated_gaussian_is_eq9():
     got = R.fourier_recursive(f, sigma_s, fit.d, T, smooth=lambda X: _smooth_separable(X, w1))
     want = oracle.fourier(f, "gaussian", sigma_s, W, fit.d, T)
     assert np.abs(got - want).max() < 1e-9
+
+
+@pytest.mark.parametrize("sigma", [64.0, 256.0])
+def test_recursion_at_the_largest_supported_sigma_equals_the_direct_sum(sigma):
+    """At the library's largest sigma_s (256) the fourth-order recursion's
+    poles come close to 1; on a line it must still match the direct sum over
+    the same kernel h (half-sample symmetric extension) to within 1e-5 of the
+    signal range per pass."""
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0, 255, 1500)
+    M = R.margin(sigma)
+    h = R.deriche_kernel(sigma, M)
+    xp = np.pad(x, M, mode="symmetric")
+    direct = np.convolve(xp, h, mode="valid")
+    rec = R.recursive_smooth_1d(x, sigma)
+    assert direct.shape == rec.shape == x.shape
+    assert np.abs(rec - direct).max() < 255 * 1e-5
