@@ -335,11 +335,11 @@ int bf_dynamic_range(const float* src, int height, int width, int src_pitch, int
  *               (same contract as for bf_filter), otherwise phases are
  *               computed per pixel in float64
  *   workspace   device memory of at least bf_recursive_workspace_bytes(job)
- *               bytes (24 (K + 1) per pixel: the row-smoothed planes of every
- *               harmonic and each harmonic's float32 shares of numerator and
- *               denominator), 256-byte
- *               aligned, owned by the caller, not overlapping src or dst; in
- *               use until the stream has passed the launches
+ *               bytes (32 (K + 1) per pixel: the float32 row-smoothed planes
+ *               of every harmonic and each harmonic's float64 shares of
+ *               numerator and denominator), 256-byte aligned, owned by the
+ *               caller, not overlapping src or dst; in use until the stream
+ *               has passed the launches
  *   hip_stream  stream to enqueue on: three launches, asynchronous
  * Returns BF_OK, BF_FIT_NOT_CONVERGED, BF_E_INVALID, BF_E_UNSUPPORTED,
  * BF_E_WORKSPACE or BF_E_DEVICE; nothing is enqueued on a negative status.

@@ -59,12 +59,10 @@ __device__ __forceinline__ void box_tile(const JobDesc& job, int X0, int Y0, uns
   }
   for (int t = tid; t <= 2 * W; t += kThreads) w1s[t] = job.w1[t];
   // stage the haloed tile: rows Y0 - W .., columns X0 - W .., folded borders
-  for (int idx = tid; idx < R * (kCols + 2 * W); idx += kThreads) {
-    const int r = idx / (kCols + 2 * W), c = idx - r * (kCols + 2 * W);
-    float v = job.src[(size_t)fold(Y0 - W + r, H_img) * job.src_pitch + fold(X0 - W + c, W_img)];
+  stage_tile<kThreads>(job.src, job.src_pitch, R, kCols + 2 * W, Y0 - W, X0 - W, H_img, W_img, [&](int r, int c, float v) {
     v = fminf(fmaxf(v, 0.f), (float)F);  // NaN -> 0; the flag promises integers in [0, F]
     ft[r][c] = (uint16_t)(int)v;
-  }
+  });
 
   // row-sum thread: row hr, 32-column half hs; column-sum thread: column vx,
   // 16-row quarter vq

@@ -169,6 +169,39 @@ __device__ __forceinline__ int fold(int i, int n) {
   return min(max(i, 0), n - 1);
 }
 
+// Stage a rows x cols block of the image starting at (y0, x0), folded at the
+// borders: element (r, c) is read and handed to put(r, c, v).  Each thread
+// issues kStageBatch independent global reads before it uses any of them, so
+// their latencies overlap (one read and wait per element would serialise a
+// full memory round trip per element).
+constexpr int kStageBatch = 16;
+template <int NTHREADS, typename Put>
+__device__ __forceinline__ void stage_tile(const float* src, int pitch, int rows, int cols, int y0, int x0, int H,
+                                           int Wd, Put put) {
+  const __attribute__((address_space(1))) float* g = (const __attribute__((address_space(1))) float*)src;
+  // element idx = r * cols + c; a thread's elements are NTHREADS apart
+  const int dr = NTHREADS / cols, dc = NTHREADS - dr * cols;
+  int r = (int)threadIdx.x / cols, c = (int)threadIdx.x - r * cols;
+  while (r < rows) {
+    float v[kStageBatch];
+    int rc[kStageBatch];
+#pragma unroll
+    for (int b = 0; b < kStageBatch; ++b) {
+      rc[b] = (r << 16) | c;
+      v[b] = r < rows ? g[(size_t)fold(y0 + r, H) * pitch + fold(x0 + c, Wd)] : 0.f;
+      r += dr;
+      c += dc;
+      if (c >= cols) {
+        c -= cols;
+        ++r;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kStageBatch; ++b)
+      if ((rc[b] >> 16) < rows) put(rc[b] >> 16, rc[b] & 0xffff, v[b]);
+  }
+}
+
 __device__ __forceinline__ float fma_acc(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ double fma_acc(double a, double b, double c) { return fma(a, b, c); }
 
@@ -401,12 +434,11 @@ __device__ __forceinline__ void fused_tile(const JobDesc& job, int X0, int Y0, u
   }
   for (int t = tid; t <= 2 * W; t += NTHR) w1s[t] = job.w1[t];
   if constexpr (INTEGER) {
-    for (int idx = tid; idx < FROWS * LWU; idx += NTHR) {
-      const int r = idx / LWU, c = idx - r * LWU;
-      float v = src[(size_t)fold(Y0 - W + r, H) * sp + fold(X0 - Wal + c, Wd)];
-      v = fminf(fmaxf(v, 0.f), (float)job.F);  // NaN -> 0; the flag promises integers in [0, F]
+    const float Fm = (float)job.F;
+    stage_tile<NTHR>(src, sp, FROWS, LWU, Y0 - W, X0 - Wal, H, Wd, [&](int r, int c, float v) {
+      v = fminf(fmaxf(v, 0.f), Fm);  // NaN -> 0; the flag promises integers in [0, F]
       ftile[r][c] = (uint16_t)((int)v * kTabBytes);
-    }
+    });
   }
   __syncthreads();
 

@@ -3,21 +3,28 @@
 // launches, the harmonics k = 0..K side by side in the grid (blockIdx.y):
 //   1. rows:    one lane per (image row, k), 64 rows staged through LDS
 //               together, modulates f into the four planes
-//               f cos, f sin, cos, sin of k w f (w = pi / T) and runs the
+//               (f - c0) cos, (f - c0) sin, cos, sin of k w f (w = pi / T,
+//               c0 the centre of the gray-level range) and runs the
 //               causal and anti-causal fourth-order recursions over the row
 //               (half-sample symmetric extension), writing the row-smoothed
 //               planes of harmonic k;
 //   2. columns: one lane per (image column, k) runs the same recursions down
 //               the row-smoothed planes and demodulates with d_k: harmonic k's
-//               share of the numerator, cos S(f cos) + sin S(f sin), and of
+//               share of the numerator, cos S((f - c0) cos) + sin S((f - c0) sin), and of
 //               the denominator, cos S(cos) + sin S(sin), times d_k (the
 //               causal and anti-causal halves of S demodulated one after the
 //               other into the same shares);
-//   3. one lane per pixel sums the K + 1 shares in float64 and divides.
-// The recursions' state is float64; the phases are float64, except in the
-// row pass of integer images, which looks cos and sin of pi m / T up in a
-// float32 table (m = k f mod 2T); the planes and shares between the launches
-// are float32.  The recursion coefficients come from the four poles of
+//   3. one lane per pixel sums the K + 1 shares in float64, divides and adds c0.
+// The recursions' state is float64; so are the phases: computed per pixel,
+// or for integer images looked up in a table of cos and sin of pi m / T
+// (m = k f mod 2T), float32 in the row pass and float64 in the column pass'
+// demodulation; the row-smoothed planes between the launches
+// are float32, the shares float64 (the denominator of a wide spatial kernel
+// can be a small difference of much larger shares, which float32 shares would
+// leave with errors above 1e-3 gray levels).  Centring f on c0 halves the
+// magnitude of the weighted planes and so their rounding.  Every lane reads
+// the values of several positions before it uses any of them, so that the
+// memory latency of a recursion step overlaps the arithmetic of the others.  The recursion coefficients come from the four poles of
 // Deriche's two damped cosine/sine pairs (his published fit of exp(-x^2/2)):
 // the causal half of the kernel is a sum of four one-pole terms, whose common
 // denominator and numerator give the recursion, and the anti-causal half
@@ -53,10 +60,11 @@ struct RecArgs {
   int T;
   int K;
   int integer;     // BF_FLAG_INTEGER_INPUT: phases of the row pass from a table
+  float c0;        // centre of the gray-level range
   RecCoef c;
   float* rows;     // [K + 1][4][height][width], row-smoothed planes
-  float* P;        // [K + 1][height][width], numerator shares
-  float* Q;        // [K + 1][height][width], denominator shares
+  double* P;       // [K + 1][height][width], numerator shares
+  double* Q;       // [K + 1][height][width], denominator shares
   double d[BF_MAX_K + 1];   // d_0..d_K
 };
 
@@ -113,8 +121,12 @@ RecCoef recursion_coefficients(double sigma) {
   return c;
 }
 
-// half-sample symmetric extension of a line of length L, any index
+// half-sample symmetric extension of a line of length L, any index (the
+// integer remainder only for indices more than a line length outside it)
 __device__ __forceinline__ int fold(int i, int L) {
+  if ((unsigned)i < (unsigned)L) return i;
+  if (i < 0 && i >= -L) return -i - 1;
+  if (i >= L && i < 2 * L) return 2 * L - 1 - i;
   const int P = 2 * L;
   int j = i % P;
   if (j < 0) j += P;
@@ -134,6 +146,7 @@ __device__ __forceinline__ void phase(float f, int k, int T, double* c, double* 
 constexpr int kChunk = 16;
 constexpr int kTileStride = kChunk + 1;   // odd stride: a lane per row hits distinct banks
 constexpr int kRowsPerPass = kLineThreads / kChunk;   // rows one block transfer instruction covers
+constexpr int kBlockRows = kLineThreads / kRowsPerPass;  // block transfer instructions per lane
 static_assert(kLineThreads % kChunk == 0, "block transfers split the wavefront into whole row segments");
 
 // cos and sin of pi m / T for m = k f mod 2T, f an integer gray level; the
@@ -158,6 +171,7 @@ __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a)
   float* outk = a.rows + 4 * plane * k;
   // in block transfers lane = (row offset r0, position q)
   const int q = lane % kChunk, r0 = lane / kChunk;
+  const double c0 = a.c0;
   if (a.integer) {
     for (int m = lane; m < 2 * a.T; m += kLineThreads) {
       double c, s;
@@ -173,8 +187,15 @@ __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a)
     const int n = min(kChunk, L - i0);
     if (q < n) {
       const int col = fold(i0 + q, L);
-      for (int r = r0; r < nrows; r += kRowsPerPass)
-        ft[r * kTileStride + q] = a.src[(size_t)(y0 + r) * a.src_pitch + col];
+      float v[kBlockRows];
+#pragma unroll
+      for (int t = 0; t < kBlockRows; ++t) {
+        const int r = r0 + t * kRowsPerPass;
+        v[t] = r < nrows ? a.src[(size_t)(y0 + r) * a.src_pitch + col] : 0.f;
+      }
+#pragma unroll
+      for (int t = 0; t < kBlockRows; ++t)
+        if (r0 + t * kRowsPerPass < nrows) ft[(r0 + t * kRowsPerPass) * kTileStride + q] = v[t];
     }
     __syncthreads();
     if (lane < nrows) {
@@ -188,7 +209,8 @@ __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a)
         } else {
           phase(f, k, a.T, &c, &s);
         }
-        const double x[4] = {f * c, f * s, c, s};
+        const double fc = (double)f - c0;
+        const double x[4] = {fc * c, fc * s, c, s};
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
           xh[p][3] = xh[p][2];
@@ -224,12 +246,29 @@ __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a)
     if (q < n) {
       const int i = lo + q;
       const int col = fold(i, L);
-      for (int r = r0; r < nrows; r += kRowsPerPass) {
-        ft[r * kTileStride + q] = a.src[(size_t)(y0 + r) * a.src_pitch + col];
-        if (i < L) {
+      // the block's f and causal halves, read in two batches of half the rows
 #pragma unroll
-          for (int p = 0; p < 4; ++p)
-            ot[(p * kLineThreads + r) * kTileStride + q] = outk[p * plane + (size_t)(y0 + r) * L + i];
+      for (int h = 0; h < 2; ++h) {
+        constexpr int HB = kBlockRows / 2;
+        float v[HB], o[4][HB];
+#pragma unroll
+        for (int t = 0; t < HB; ++t) {
+          const int r = r0 + (h * HB + t) * kRowsPerPass;
+          const bool ok = r < nrows;
+          v[t] = ok ? a.src[(size_t)(y0 + r) * a.src_pitch + col] : 0.f;
+#pragma unroll
+          for (int p = 0; p < 4; ++p) o[p][t] = (ok && i < L) ? outk[p * plane + (size_t)(y0 + r) * L + i] : 0.f;
+        }
+#pragma unroll
+        for (int t = 0; t < HB; ++t) {
+          const int r = r0 + (h * HB + t) * kRowsPerPass;
+          if (r < nrows) {
+            ft[r * kTileStride + q] = v[t];
+            if (i < L) {
+#pragma unroll
+              for (int p = 0; p < 4; ++p) ot[(p * kLineThreads + r) * kTileStride + q] = o[p][t];
+            }
+          }
         }
       }
     }
@@ -245,7 +284,8 @@ __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a)
         } else {
           phase(f, k, a.T, &c, &s);
         }
-        const double x[4] = {f * c, f * s, c, s};
+        const double fc = (double)f - c0;
+        const double x[4] = {fc * c, fc * s, c, s};
         const bool inside = lo + j < L;
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
@@ -281,69 +321,126 @@ __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a)
 // The column pass demodulates the causal and the anti-causal halves of each
 // smoothed plane separately (demodulation is linear): the causal sweep writes
 // harmonic k's shares of numerator and denominator from its half, and the
-// anti-causal sweep adds its own, so no causal half is stored.
+// anti-causal sweep adds its own, so no causal half is stored.  Each sweep
+// reads kColAhead positions at a time before it runs their recursion steps.
+// For integer images the demodulation's cos and sin of pi m / T,
+// m = k f mod 2T, come from a float64 table in LDS built by the workgroup.
+constexpr int kColAhead = 8;
 __global__ void __launch_bounds__(kLineThreads) rec_cols_kernel(const RecArgs a) {
+  extern __shared__ double2 dcs_tab[];  // 2T entries (cos, sin) when a.integer
   const int x0 = blockIdx.x * kLineThreads + threadIdx.x;
   const int k = blockIdx.y;
+  if (a.integer) {
+    for (int m = threadIdx.x; m < 2 * a.T; m += kLineThreads) {
+      double c, s;
+      sincospi(static_cast<double>(m) / a.T, &s, &c);
+      dcs_tab[m] = make_double2(c, s);
+    }
+    __syncthreads();
+  }
   if (x0 >= a.width) return;
+  // cos and sin of k pi f / T for this column's pixels
+  auto demod_phase = [&](float f, double* c, double* s) {
+    if (a.integer) {
+      const int T2 = 2 * a.T;
+      const float fc = fminf(fmaxf(f, 0.0f), 1.0e6f);
+      const int m = static_cast<int>((static_cast<long long>(k) * static_cast<long long>(fc)) % T2);
+      const double2 cs = dcs_tab[m];
+      *c = cs.x;
+      *s = cs.y;
+    } else {
+      phase(f, k, a.T, c, s);
+    }
+  };
   const int L = a.height, M = a.c.margin, Wd = a.width;
   const size_t plane = (size_t)a.height * a.width;
   const float* in = a.rows + 4 * plane * k + x0;
   const double dk = a.d[k];
   double xh[4][4] = {};
   double yh[4][4] = {};
-  for (int i = -M; i < L; ++i) {
-    const size_t r = (size_t)fold(i, L) * Wd;
-    double S[4];
+  for (int i0 = -M; i0 < L; i0 += kColAhead) {
+    float xin[kColAhead][4], fs[kColAhead];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      xh[p][3] = xh[p][2];
-      xh[p][2] = xh[p][1];
-      xh[p][1] = xh[p][0];
-      xh[p][0] = in[p * plane + r];
-      const double v = a.c.nc[0] * xh[p][0] + a.c.nc[1] * xh[p][1] + a.c.nc[2] * xh[p][2] + a.c.nc[3] * xh[p][3] -
-                       a.c.dd[1] * yh[p][0] - a.c.dd[2] * yh[p][1] - a.c.dd[3] * yh[p][2] - a.c.dd[4] * yh[p][3];
-      yh[p][3] = yh[p][2];
-      yh[p][2] = yh[p][1];
-      yh[p][1] = yh[p][0];
-      yh[p][0] = v;
-      S[p] = v;
+    for (int j = 0; j < kColAhead; ++j) {
+      const int i = i0 + j;
+      const size_t r = (size_t)fold(i, L) * Wd;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) xin[j][p] = i < L ? in[p * plane + r] : 0.f;
+      fs[j] = (i >= 0 && i < L) ? a.src[(size_t)i * a.src_pitch + x0] : 0.f;
     }
-    if (i >= 0) {
-      const float f = a.src[(size_t)i * a.src_pitch + x0];
-      double c, s;
-      phase(f, k, a.T, &c, &s);
-      const size_t o = plane * k + (size_t)i * Wd + x0;
-      a.P[o] = static_cast<float>(dk * (c * S[0] + s * S[1]));
-      a.Q[o] = static_cast<float>(dk * (c * S[2] + s * S[3]));
+#pragma unroll
+    for (int j = 0; j < kColAhead; ++j) {
+      const int i = i0 + j;
+      if (i >= L) break;
+      double S[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        xh[p][3] = xh[p][2];
+        xh[p][2] = xh[p][1];
+        xh[p][1] = xh[p][0];
+        xh[p][0] = xin[j][p];
+        const double v = a.c.nc[0] * xh[p][0] + a.c.nc[1] * xh[p][1] + a.c.nc[2] * xh[p][2] +
+                         a.c.nc[3] * xh[p][3] - a.c.dd[1] * yh[p][0] - a.c.dd[2] * yh[p][1] -
+                         a.c.dd[3] * yh[p][2] - a.c.dd[4] * yh[p][3];
+        yh[p][3] = yh[p][2];
+        yh[p][2] = yh[p][1];
+        yh[p][1] = yh[p][0];
+        yh[p][0] = v;
+        S[p] = v;
+      }
+      if (i >= 0) {
+        double c, s;
+        demod_phase(fs[j], &c, &s);
+        const size_t o = plane * k + (size_t)i * Wd + x0;
+        a.P[o] = dk * (c * S[0] + s * S[1]);
+        a.Q[o] = dk * (c * S[2] + s * S[3]);
+      }
     }
   }
   double xa[4][4] = {};
   double ya[4][4] = {};
-  for (int i = L - 1 + M; i >= 0; --i) {
-    const size_t r = (size_t)fold(i, L) * Wd;
-    double S[4];
+  for (int i0 = L - 1 + M; i0 >= 0; i0 -= kColAhead) {
+    float xin[kColAhead][4], fs[kColAhead];
+    double po[kColAhead], qo[kColAhead];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const double v = a.c.na[1] * xa[p][0] + a.c.na[2] * xa[p][1] + a.c.na[3] * xa[p][2] + a.c.na[4] * xa[p][3] -
-                       a.c.dd[1] * ya[p][0] - a.c.dd[2] * ya[p][1] - a.c.dd[3] * ya[p][2] - a.c.dd[4] * ya[p][3];
-      ya[p][3] = ya[p][2];
-      ya[p][2] = ya[p][1];
-      ya[p][1] = ya[p][0];
-      ya[p][0] = v;
-      xa[p][3] = xa[p][2];
-      xa[p][2] = xa[p][1];
-      xa[p][1] = xa[p][0];
-      xa[p][0] = in[p * plane + r];
-      S[p] = v;
+    for (int j = 0; j < kColAhead; ++j) {
+      const int i = i0 - j;
+      const size_t r = (size_t)fold(i, L) * Wd;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) xin[j][p] = i >= 0 ? in[p * plane + r] : 0.f;
+      const bool out = i >= 0 && i < L;
+      const size_t o = plane * k + (size_t)(out ? i : 0) * Wd + x0;
+      fs[j] = out ? a.src[(size_t)i * a.src_pitch + x0] : 0.f;
+      po[j] = out ? a.P[o] : 0.0;
+      qo[j] = out ? a.Q[o] : 0.0;
     }
-    if (i < L) {
-      const float f = a.src[(size_t)i * a.src_pitch + x0];
-      double c, s;
-      phase(f, k, a.T, &c, &s);
-      const size_t o = plane * k + (size_t)i * Wd + x0;
-      a.P[o] = static_cast<float>((double)a.P[o] + dk * (c * S[0] + s * S[1]));
-      a.Q[o] = static_cast<float>((double)a.Q[o] + dk * (c * S[2] + s * S[3]));
+#pragma unroll
+    for (int j = 0; j < kColAhead; ++j) {
+      const int i = i0 - j;
+      if (i < 0) break;
+      double S[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const double v = a.c.na[1] * xa[p][0] + a.c.na[2] * xa[p][1] + a.c.na[3] * xa[p][2] +
+                         a.c.na[4] * xa[p][3] - a.c.dd[1] * ya[p][0] - a.c.dd[2] * ya[p][1] -
+                         a.c.dd[3] * ya[p][2] - a.c.dd[4] * ya[p][3];
+        ya[p][3] = ya[p][2];
+        ya[p][2] = ya[p][1];
+        ya[p][1] = ya[p][0];
+        ya[p][0] = v;
+        xa[p][3] = xa[p][2];
+        xa[p][2] = xa[p][1];
+        xa[p][1] = xa[p][0];
+        xa[p][0] = xin[j][p];
+        S[p] = v;
+      }
+      if (i < L) {
+        double c, s;
+        demod_phase(fs[j], &c, &s);
+        const size_t o = plane * k + (size_t)i * Wd + x0;
+        a.P[o] = po[j] + dk * (c * S[0] + s * S[1]);
+        a.Q[o] = qo[j] + dk * (c * S[2] + s * S[3]);
+      }
     }
   }
 }
@@ -358,15 +455,15 @@ __global__ void __launch_bounds__(256) rec_sum_kernel(const RecArgs a) {
     q += a.Q[n * k + o];
   }
   const int y = static_cast<int>(o / a.width), x = static_cast<int>(o % a.width);
-  a.dst[(size_t)y * a.dst_pitch + x] = static_cast<float>(p / q);
+  a.dst[(size_t)y * a.dst_pitch + x] = static_cast<float>(p / q + (double)a.c0);
 }
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-// layout: row-smoothed planes, numerator shares, denominator shares
+// layout: row-smoothed planes (float32), numerator shares, denominator shares (float64)
 size_t rec_ws_bytes(int height, int width, int K) {
   const size_t n = (size_t)height * width, h = (size_t)K + 1;
-  return align256(4 * h * n * sizeof(float)) + 2 * align256(h * n * sizeof(float));
+  return align256(4 * h * n * sizeof(float)) + 2 * align256(h * n * sizeof(double));
 }
 
 }  // namespace
@@ -417,19 +514,21 @@ extern "C" int bf_filter_recursive(const bf_job* job, void* workspace, size_t ws
   a.dst_pitch = job->dst_pitch;
   a.T = job->T;
   a.integer = (job->flags & BF_FLAG_INTEGER_INPUT) ? 1 : 0;
+  a.c0 = r.desc.c0;
   a.c = recursion_coefficients(job->sigma_s);
   a.K = K;
-  const size_t planes = align256(4 * h * n * sizeof(float)), shares = align256(h * n * sizeof(float));
+  const size_t planes = align256(4 * h * n * sizeof(float)), shares = align256(h * n * sizeof(double));
   a.rows = reinterpret_cast<float*>(w);
-  a.P = reinterpret_cast<float*>(w + planes);
-  a.Q = reinterpret_cast<float*>(w + planes + shares);
+  a.P = reinterpret_cast<double*>(w + planes);
+  a.Q = reinterpret_cast<double*>(w + planes + shares);
   for (int k = 0; k <= K; ++k) a.d[k] = r.desc.d[k];
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
   const dim3 grows((job->height + kLineThreads - 1) / kLineThreads, K + 1);
   const dim3 gcols((job->width + kLineThreads - 1) / kLineThreads, K + 1);
   const size_t tab_bytes = a.integer ? 2 * (size_t)job->T * sizeof(float2) : 0;
   hipLaunchKernelGGL(rec_rows_kernel, grows, dim3(kLineThreads), tab_bytes, stream, a);
-  hipLaunchKernelGGL(rec_cols_kernel, gcols, dim3(kLineThreads), 0, stream, a);
+  hipLaunchKernelGGL(rec_cols_kernel, gcols, dim3(kLineThreads), a.integer ? 2 * (size_t)job->T * sizeof(double2) : 0,
+                     stream, a);
   hipLaunchKernelGGL(rec_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(BF_E_DEVICE, std::string("recursive-filter launch failed: ") + hipGetErrorString(e));

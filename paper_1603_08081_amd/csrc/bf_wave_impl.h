@@ -125,13 +125,10 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
   }
   for (int t = tid; t <= 2 * W; t += kWaveThreads) w1s[t] = job.w1[t];
   // stage the haloed tile once: folded borders, f clamped to [0, F]
-  for (int idx = tid; idx < FROWS * LWU; idx += kWaveThreads) {
-    const int r = idx / LWU, c = idx - r * LWU;
-    float v = src[(size_t)fold(Y0 - W + r, H) * sp + fold(X0 - Wal + c, Wd)];
+  stage_tile<kWaveThreads>(src, sp, FROWS, LWU, Y0 - W, X0 - Wal, H, Wd, [&](int r, int c, float v) {
     v = fminf(fmaxf(v, 0.f), (float)F);  // NaN -> 0; the flag promises integers in [0, F]
-    const int f = (int)v;
-    ftile[r][c] = (uint16_t)(f * MODB);
-  }
+    ftile[r][c] = (uint16_t)((int)v * MODB);
+  });
   __syncthreads();
 
   auto wq = [&](int dd) -> float { return (dd >= -W && dd <= W) ? PT::round(w1s[dd + W]) : 0.f; };
@@ -357,12 +354,10 @@ __device__ __forceinline__ void wave_tile_wide(const JobDesc& job, int X0, int Y
   for (int t = tid; t <= 2 * W; t += kWaveThreads) w1s[t] = job.w1[t];
   // stage the haloed tile once: folded borders, f clamped to [0, F], stored
   // as the address of the pixel's entry in the first modulation table
-  for (int idx = tid; idx < FROWS * LWU; idx += kWaveThreads) {
-    const int r = idx / LWU, c = idx - r * LWU;
-    float v = src[(size_t)fold(Y0 - W + r, H) * sp + fold(X0 - Wal + c, Wd)];
+  stage_tile<kWaveThreads>(src, sp, FROWS, LWU, Y0 - W, X0 - Wal, H, Wd, [&](int r, int c, float v) {
     v = fminf(fmaxf(v, 0.f), (float)F);  // NaN -> 0; the flag promises integers in [0, F]
     ftile[r][c] = tb + (uint32_t)((int)v * MODB);
-  }
+  });
   __syncthreads();
 
   auto wq = [&](int dd) -> float { return (dd >= -W && dd <= W) ? PT::round(w1s[dd + W]) : 0.f; };

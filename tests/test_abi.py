@@ -312,7 +312,7 @@ def test_recursive_filter_workspace_checks():
     # 24 (K + 1) bytes per pixel (row-smoothed planes, numerator and
     # denominator shares), each of the three regions 256-byte aligned
     j = _job(W=0, d=np.array([1.0, 0.5, 0.25]))
-    assert native.bf_recursive_workspace_bytes(j) == 24 * 3 * 64 * 64
+    assert native.bf_recursive_workspace_bytes(j) == 32 * 3 * 64 * 64
     assert native.bf_recursive_workspace_bytes(_job(W=0, d=np.array([1.0]), height=3, width=5)) == 3 * 256
     ws = native.bf_recursive_workspace_bytes(j)
     for ptr, n in ((None, ws), (0x30000000, ws - 1), (0x30000004, ws)):

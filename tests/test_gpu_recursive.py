@@ -113,3 +113,22 @@ def test_matches_eq9_with_the_direct_sum_smoothing():
     err = np.abs(out - want).max()
     print("recursive vs eq. (9) with direct-sum smoothing: %.3g" % err, flush=True)
     assert err <= TOL
+
+
+@pytest.mark.parametrize("sigma_s,rows,cols", [(24.0, 512, 768), (256.0, 96, 128)])
+def test_wide_spatial_kernels_on_a_crop_of_the_uhd_workload(sigma_s, rows, cols):
+    """Spatial kernels wider than the truncated path reaches (W > 64), on the
+    UHD workload's own content (K = 32, sigma_r = 15): with a wide kernel the
+    denominator falls to a few 1e-4 at pixels unlike their surroundings, and
+    the error of each harmonic's share is amplified by its inverse, so every
+    pixel is compared."""
+    from synth import workload_images
+    f = np.ascontiguousarray(workload_images("frames32_2160x3840", limit=1)[0][:rows, :cols], dtype=np.float32)
+    fit = oracle.fit_kernel("gaussian", 15.0, 255, 0.0, 32)
+    print("recursive sigma_s", sigma_s, "crop", rows, cols, flush=True)
+    out, st = _run(f, sigma_s=sigma_s, T=255, d=fit.d, integer_input=True)
+    want = R.fourier_recursive(f, sigma_s, fit.d, 255)
+    err = np.abs(out - want).max()
+    print("recursive sigma_s %g: max err over every pixel %.3g" % (sigma_s, err), flush=True)
+    assert st == 0
+    assert err <= TOL
