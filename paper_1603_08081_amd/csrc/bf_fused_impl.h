@@ -171,14 +171,48 @@ __device__ __forceinline__ int fold(int i, int n) {
 
 // Stage a rows x cols block of the image starting at (y0, x0), folded at the
 // borders: element (r, c) is read and handed to put(r, c, v).  Each thread
-// issues kStageBatch independent global reads before it uses any of them, so
+// issues a batch of independent global reads before it uses any of them, so
 // their latencies overlap (one read and wait per element would serialise a
-// full memory round trip per element).
+// full memory round trip per element).  Blocks whose columns lie inside the
+// image, start 16-byte aligned and span a multiple of 4 columns are read as
+// float4 (one batch covers a whole tile of the 16-bit kernels); others
+// element by element with the border fold.
 constexpr int kStageBatch = 16;
+constexpr int kStageBatch4 = 24;
 template <int NTHREADS, typename Put>
 __device__ __forceinline__ void stage_tile(const float* src, int pitch, int rows, int cols, int y0, int x0, int H,
                                            int Wd, Put put) {
   const __attribute__((address_space(1))) float* g = (const __attribute__((address_space(1))) float*)src;
+  if (x0 >= 0 && x0 + cols <= Wd && (cols & 3) == 0 && (pitch & 3) == 0 &&
+      ((reinterpret_cast<uintptr_t>(src) + 4 * (uintptr_t)x0) & 15) == 0) {
+    const int q4 = cols >> 2, n4 = rows * q4;
+    for (int base = (int)threadIdx.x; base < n4; base += kStageBatch4 * NTHREADS) {
+      typedef float f4v __attribute__((ext_vector_type(4)));
+      f4v v[kStageBatch4];
+#pragma unroll
+      for (int b = 0; b < kStageBatch4; ++b) {
+        const int idx = base + b * NTHREADS;
+        v[b] = f4v{0.f, 0.f, 0.f, 0.f};
+        if (idx < n4) {
+          const int r = idx / q4, c4 = idx - r * q4;
+          v[b] = *reinterpret_cast<const __attribute__((address_space(1))) f4v*>(
+              g + (size_t)fold(y0 + r, H) * pitch + x0 + 4 * c4);
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < kStageBatch4; ++b) {
+        const int idx = base + b * NTHREADS;
+        if (idx < n4) {
+          const int r = idx / q4, c = 4 * (idx - r * q4);
+          put(r, c, v[b].x);
+          put(r, c + 1, v[b].y);
+          put(r, c + 2, v[b].z);
+          put(r, c + 3, v[b].w);
+        }
+      }
+    }
+    return;
+  }
   // element idx = r * cols + c; a thread's elements are NTHREADS apart
   const int dr = NTHREADS / cols, dc = NTHREADS - dr * cols;
   int r = (int)threadIdx.x / cols, c = (int)threadIdx.x - r * cols;
@@ -201,6 +235,55 @@ __device__ __forceinline__ void stage_tile(const float* src, int pitch, int rows
       if ((rc[b] >> 16) < rows) put(rc[b] >> 16, rc[b] & 0xffff, v[b]);
   }
 }
+
+// Read-ahead of one tile's block into registers: the float4 path of
+// stage_tile split into issue() (the reads start) and commit() (the values go
+// to put(r, c, v)), so that a persistent workgroup can start the reads of its
+// next tile before it finishes the current one.  Blocks that do not take the
+// float4 path or need more than NB float4 per thread are not read ahead.
+template <int NTHREADS, int NB>
+struct TileReadAhead {
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  f4v v[NB];
+  bool valid;
+  __device__ static bool eligible(const float* src, int pitch, int rows, int cols, int x0, int Wd) {
+    return x0 >= 0 && x0 + cols <= Wd && (cols & 3) == 0 && (pitch & 3) == 0 &&
+           ((reinterpret_cast<uintptr_t>(src) + 4 * (uintptr_t)x0) & 15) == 0 && rows * (cols >> 2) <= NB * NTHREADS;
+  }
+  __device__ void issue(const float* src, int pitch, int rows, int cols, int y0, int x0, int H) {
+    const __attribute__((address_space(1))) float* g = (const __attribute__((address_space(1))) float*)src;
+    const int q4 = cols >> 2, n4 = rows * q4;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int idx = (int)threadIdx.x + b * NTHREADS;
+      v[b] = f4v{0.f, 0.f, 0.f, 0.f};
+      if (idx < n4) {
+        const int r = idx / q4, c4 = idx - r * q4;
+        v[b] = *reinterpret_cast<const __attribute__((address_space(1))) f4v*>(g + (size_t)fold(y0 + r, H) * pitch +
+                                                                                 x0 + 4 * c4);
+      }
+    }
+  }
+  __device__ void clear() {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) v[b] = f4v{0.f, 0.f, 0.f, 0.f};
+  }
+  template <typename Put>
+  __device__ void commit(int rows, int cols, Put put) const {
+    const int q4 = cols >> 2, n4 = rows * q4;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int idx = (int)threadIdx.x + b * NTHREADS;
+      if (idx < n4) {
+        const int r = idx / q4, c = 4 * (idx - r * q4);
+        put(r, c, v[b].x);
+        put(r, c + 1, v[b].y);
+        put(r, c + 2, v[b].z);
+        put(r, c + 3, v[b].w);
+      }
+    }
+  }
+};
 
 __device__ __forceinline__ float fma_acc(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ double fma_acc(double a, double b, double c) { return fma(a, b, c); }

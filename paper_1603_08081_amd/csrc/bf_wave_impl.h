@@ -71,6 +71,9 @@ struct WideLds {
   static constexpr int FROWS = 16 * (TH / 16 + NT - 1);
   static constexpr size_t tile = (size_t)FROWS * FW * 4;
   static constexpr size_t total = tile + 4 * (2 * BF_MAX_W + 1) + 64;
+  // float4 per thread that read one staged tile ahead
+  static constexpr int RA = (FROWS * (G::LWU / 4) + kWaveThreads - 1) / kWaveThreads;
+  using ReadAhead = TileReadAhead<kWaveThreads, RA>;
 };
 // dynamic LDS of the wide layout: cos/sin(pi m / T) [2T x 8 B], then the four
 // tables at kWideSpan strides
@@ -322,9 +325,13 @@ __device__ __forceinline__ void wave_tile(const JobDesc& job, int X0, int Y0, ui
 // results.  tab points at the four tables (kWideSpan apart); the job's gray
 // levels must lie in 0..255.  Harmonics run as odd/even pairs so that each
 // body knows its table parity at compile time.
+// ra: the reads of this tile when ra.valid (started by the previous tile), and
+// on return those of the tile at (nX0, nY0) of *next when next is set.
 template <int PREC, int NT, int TH>
 __device__ __forceinline__ void wave_tile_wide(const JobDesc& job, int X0, int Y0, uint32_t* ftile_raw, float* w1s,
-                                               unsigned char* tab, float2* lut, bool build_lut) {
+                                               unsigned char* tab, float2* lut, bool build_lut,
+                                               typename WideLds<PREC, NT, TH>::ReadAhead& ra, const JobDesc* next,
+                                               int nX0, int nY0) {
   using G = WaveGeo<PREC, NT>;
   using L = WideLds<PREC, NT, TH>;
   using PT = Planes<PREC>;
@@ -354,10 +361,12 @@ __device__ __forceinline__ void wave_tile_wide(const JobDesc& job, int X0, int Y
   for (int t = tid; t <= 2 * W; t += kWaveThreads) w1s[t] = job.w1[t];
   // stage the haloed tile once: folded borders, f clamped to [0, F], stored
   // as the address of the pixel's entry in the first modulation table
-  stage_tile<kWaveThreads>(src, sp, FROWS, LWU, Y0 - W, X0 - Wal, H, Wd, [&](int r, int c, float v) {
+  auto put = [&](int r, int c, float v) {
     v = fminf(fmaxf(v, 0.f), (float)F);  // NaN -> 0; the flag promises integers in [0, F]
     ftile[r][c] = tb + (uint32_t)((int)v * MODB);
-  });
+  };
+  if (ra.valid) ra.commit(FROWS, LWU, put);
+  else stage_tile<kWaveThreads>(src, sp, FROWS, LWU, Y0 - W, X0 - Wal, H, Wd, put);
   __syncthreads();
 
   auto wq = [&](int dd) -> float { return (dd >= -W && dd <= W) ? PT::round(w1s[dd + W]) : 0.f; };
@@ -543,7 +552,6 @@ __device__ __forceinline__ void wave_tile_wide(const JobDesc& job, int X0, int Y
     __syncthreads();
     run(std::integral_constant<int, 4>{}, std::integral_constant<int, 1>{});
   }
-
   float* __restrict__ dst = job.dst;
   for (int j = 0; j < NJ; ++j) {
     const int yy = Y0 + 16 * j + n16;
@@ -557,6 +565,18 @@ __device__ __forceinline__ void wave_tile_wide(const JobDesc& job, int X0, int Y
   const unsigned long long fl = refine_flags<NJ>(Q, job, Y0, x0, PT::kRefineQ);
   refine_tile<NJ>(fl, job, X0, Y0, Wal, w1s, lut, tab, 4 * (size_t)kWideSpan, kWaveThreads,
                   [&](int r, int c) { return (int)((ftile[r][c] - tb) >> 3); });
+  // start reading the next tile (its block lands in registers while the
+  // workgroup finishes this tile and sets up the next)
+  // (ra.v is written on every path, so that the registers of a read never
+  // committed are not kept across the next tile)
+  {
+    const int nWal = next ? (next->W + 7) & ~7 : 0;
+    ra.valid = next && WideLds<PREC, NT, TH>::ReadAhead::eligible(next->src, next->src_pitch, FROWS, LWU, nX0 - nWal,
+                                                                  next->width);
+    if (ra.valid) ra.issue(next->src, next->src_pitch, FROWS, LWU, nY0 - next->W, nX0 - nWal, next->height);
+    else ra.clear();
+  }
+
   __syncthreads();  // the LDS of this tile may be reused by the caller
 }
 
@@ -573,11 +593,14 @@ constexpr bool kWideBuildable =
 // entries pairs first, tables after it)
 template <int PREC, int NT, int TH, bool WIDE>
 __device__ __forceinline__ void wave_tile_any(const JobDesc& job, int X0, int Y0, void* ftile, float* w1s,
-                                              unsigned char* dyn, int t_lut, bool build_lut) {
+                                              unsigned char* dyn, int t_lut, bool build_lut,
+                                              typename WideLds<PREC, NT, TH>::ReadAhead& ra,
+                                              const JobDesc* next = nullptr, int nX0 = 0, int nY0 = 0) {
   float2* lut = reinterpret_cast<float2*>(dyn);
   unsigned char* tab = dyn + 16 * (size_t)t_lut;
   if constexpr (WIDE)
-    wave_tile_wide<PREC, NT, TH>(job, X0, Y0, static_cast<uint32_t*>(ftile), w1s, tab, lut, build_lut);
+    wave_tile_wide<PREC, NT, TH>(job, X0, Y0, static_cast<uint32_t*>(ftile), w1s, tab, lut, build_lut, ra, next, nX0,
+                                 nY0);
   else
     wave_tile<PREC, NT, TH>(job, X0, Y0, static_cast<uint16_t*>(ftile), w1s, tab, lut, build_lut);
 }
@@ -594,7 +617,9 @@ __global__ void __launch_bounds__(kWaveThreads) wave_kernel(const JobDesc job) {
     __shared__ __attribute__((aligned(16))) Off ftile[TILE_ELEMS];
     __shared__ float w1s[2 * BF_MAX_W + 1];
     extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
-    wave_tile_any<PREC, NT, TH, WIDE>(job, blockIdx.x * kWaveCols, blockIdx.y * TH, ftile, w1s, dyn, job.T, true);
+    typename WideLds<PREC, NT, TH>::ReadAhead ra;
+    ra.valid = false;
+    wave_tile_any<PREC, NT, TH, WIDE>(job, blockIdx.x * kWaveCols, blockIdx.y * TH, ftile, w1s, dyn, job.T, true, ra);
   }
 }
 
@@ -613,10 +638,15 @@ __global__ void __launch_bounds__(kWaveThreads) wave_batched_kernel(const JobDes
     __shared__ float w1s[2 * BF_MAX_W + 1];
     extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
     int lut_t = -1;
+    typename WideLds<PREC, NT, TH>::ReadAhead ra;
+    ra.valid = false;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
       const int4 w = items[it];
       const JobDesc& job = jobs[w.x];
-      wave_tile_any<PREC, NT, TH, WIDE>(job, w.y, w.z, ftile, w1s, dyn, t_max, job.T != lut_t);
+      const bool more = it + (int)gridDim.x < n_items;
+      const int4 nw = more ? items[it + gridDim.x] : make_int4(0, 0, 0, 0);
+      wave_tile_any<PREC, NT, TH, WIDE>(job, w.y, w.z, ftile, w1s, dyn, t_max, job.T != lut_t, ra,
+                                        more ? &jobs[nw.x] : nullptr, nw.y, nw.z);
       lut_t = job.T;
     }
   }
