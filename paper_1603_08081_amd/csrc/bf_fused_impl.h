@@ -175,35 +175,39 @@ __device__ __forceinline__ int fold(int i, int n) {
 // their latencies overlap (one read and wait per element would serialise a
 // full memory round trip per element).  Blocks whose columns lie inside the
 // image, start 16-byte aligned and span a multiple of 4 columns are read as
-// float4 (one batch covers a whole tile of the 16-bit kernels); others
-// element by element with the border fold.
+// float4: a thread keeps one column quad and steps down the rows, so that its
+// addresses need no per-element division; others element by element with the
+// border fold.
 constexpr int kStageBatch = 16;
 constexpr int kStageBatch4 = 24;
+typedef float f4v_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bool stage_vectorizable(const float* src, int pitch, int cols, int x0, int Wd) {
+  return x0 >= 0 && x0 + cols <= Wd && (cols & 3) == 0 && (pitch & 3) == 0 &&
+         ((reinterpret_cast<uintptr_t>(src) + 4 * (uintptr_t)x0) & 15) == 0;
+}
+
 template <int NTHREADS, typename Put>
 __device__ __forceinline__ void stage_tile(const float* src, int pitch, int rows, int cols, int y0, int x0, int H,
                                            int Wd, Put put) {
   const __attribute__((address_space(1))) float* g = (const __attribute__((address_space(1))) float*)src;
-  if (x0 >= 0 && x0 + cols <= Wd && (cols & 3) == 0 && (pitch & 3) == 0 &&
-      ((reinterpret_cast<uintptr_t>(src) + 4 * (uintptr_t)x0) & 15) == 0) {
-    const int q4 = cols >> 2, n4 = rows * q4;
-    for (int base = (int)threadIdx.x; base < n4; base += kStageBatch4 * NTHREADS) {
-      typedef float f4v __attribute__((ext_vector_type(4)));
-      f4v v[kStageBatch4];
+  if (stage_vectorizable(src, pitch, cols, x0, Wd) && (cols >> 2) <= NTHREADS) {
+    const int q4 = cols >> 2, rstep = NTHREADS / q4;
+    const int r0 = (int)threadIdx.x / q4, c = 4 * ((int)threadIdx.x - r0 * q4);
+    if (r0 >= rstep) return;  // threads beyond the last whole row of quads
+    for (int rb = r0; rb < rows; rb += kStageBatch4 * rstep) {
+      f4v_t v[kStageBatch4];
 #pragma unroll
       for (int b = 0; b < kStageBatch4; ++b) {
-        const int idx = base + b * NTHREADS;
-        v[b] = f4v{0.f, 0.f, 0.f, 0.f};
-        if (idx < n4) {
-          const int r = idx / q4, c4 = idx - r * q4;
-          v[b] = *reinterpret_cast<const __attribute__((address_space(1))) f4v*>(
-              g + (size_t)fold(y0 + r, H) * pitch + x0 + 4 * c4);
-        }
+        const int r = rb + b * rstep;
+        v[b] = r < rows ? *reinterpret_cast<const __attribute__((address_space(1))) f4v_t*>(
+                              g + (size_t)fold(y0 + r, H) * pitch + x0 + c)
+                        : f4v_t{0.f, 0.f, 0.f, 0.f};
       }
 #pragma unroll
       for (int b = 0; b < kStageBatch4; ++b) {
-        const int idx = base + b * NTHREADS;
-        if (idx < n4) {
-          const int r = idx / q4, c = 4 * (idx - r * q4);
+        const int r = rb + b * rstep;
+        if (r < rows) {
           put(r, c, v[b].x);
           put(r, c + 1, v[b].y);
           put(r, c + 2, v[b].z);
@@ -236,46 +240,42 @@ __device__ __forceinline__ void stage_tile(const float* src, int pitch, int rows
   }
 }
 
-// Read-ahead of one tile's block into registers: the float4 path of
-// stage_tile split into issue() (the reads start) and commit() (the values go
-// to put(r, c, v)), so that a persistent workgroup can start the reads of its
-// next tile before it finishes the current one.  Blocks that do not take the
-// float4 path or need more than NB float4 per thread are not read ahead.
-template <int NTHREADS, int NB>
+// Read-ahead of one tile's block (ROWS x COLS) into registers: the float4 path
+// of stage_tile split into issue() (the reads start) and commit() (the values
+// go to put(r, c, v)), so that a persistent workgroup can start the reads of
+// its next tile before it finishes the current one.
+template <int NTHREADS, int ROWS, int COLS>
 struct TileReadAhead {
-  typedef float f4v __attribute__((ext_vector_type(4)));
-  f4v v[NB];
+  static constexpr int Q4 = COLS / 4, RSTEP = NTHREADS / Q4, NB = (ROWS + RSTEP - 1) / RSTEP;
+  static_assert(COLS % 4 == 0 && Q4 <= NTHREADS, "a row of quads per pass");
+  f4v_t v[NB];
   bool valid;
-  __device__ static bool eligible(const float* src, int pitch, int rows, int cols, int x0, int Wd) {
-    return x0 >= 0 && x0 + cols <= Wd && (cols & 3) == 0 && (pitch & 3) == 0 &&
-           ((reinterpret_cast<uintptr_t>(src) + 4 * (uintptr_t)x0) & 15) == 0 && rows * (cols >> 2) <= NB * NTHREADS;
+  __device__ static bool eligible(const float* src, int pitch, int x0, int Wd) {
+    return stage_vectorizable(src, pitch, COLS, x0, Wd);
   }
-  __device__ void issue(const float* src, int pitch, int rows, int cols, int y0, int x0, int H) {
+  __device__ void issue(const float* src, int pitch, int y0, int x0, int H) {
     const __attribute__((address_space(1))) float* g = (const __attribute__((address_space(1))) float*)src;
-    const int q4 = cols >> 2, n4 = rows * q4;
+    const int r0 = (int)threadIdx.x / Q4, c = 4 * ((int)threadIdx.x - r0 * Q4);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const int idx = (int)threadIdx.x + b * NTHREADS;
-      v[b] = f4v{0.f, 0.f, 0.f, 0.f};
-      if (idx < n4) {
-        const int r = idx / q4, c4 = idx - r * q4;
-        v[b] = *reinterpret_cast<const __attribute__((address_space(1))) f4v*>(g + (size_t)fold(y0 + r, H) * pitch +
-                                                                                 x0 + 4 * c4);
-      }
+      const int r = r0 + b * RSTEP;
+      v[b] = (r0 < RSTEP && r < ROWS) ? *reinterpret_cast<const __attribute__((address_space(1))) f4v_t*>(
+                                            g + (size_t)fold(y0 + r, H) * pitch + x0 + c)
+                                      : f4v_t{0.f, 0.f, 0.f, 0.f};
     }
   }
   __device__ void clear() {
 #pragma unroll
-    for (int b = 0; b < NB; ++b) v[b] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < NB; ++b) v[b] = f4v_t{0.f, 0.f, 0.f, 0.f};
   }
   template <typename Put>
-  __device__ void commit(int rows, int cols, Put put) const {
-    const int q4 = cols >> 2, n4 = rows * q4;
+  __device__ void commit(Put put) const {
+    const int r0 = (int)threadIdx.x / Q4, c = 4 * ((int)threadIdx.x - r0 * Q4);
+    if (r0 >= RSTEP) return;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const int idx = (int)threadIdx.x + b * NTHREADS;
-      if (idx < n4) {
-        const int r = idx / q4, c = 4 * (idx - r * q4);
+      const int r = r0 + b * RSTEP;
+      if (r < ROWS) {
         put(r, c, v[b].x);
         put(r, c + 1, v[b].y);
         put(r, c + 2, v[b].z);

@@ -71,9 +71,7 @@ struct WideLds {
   static constexpr int FROWS = 16 * (TH / 16 + NT - 1);
   static constexpr size_t tile = (size_t)FROWS * FW * 4;
   static constexpr size_t total = tile + 4 * (2 * BF_MAX_W + 1) + 64;
-  // float4 per thread that read one staged tile ahead
-  static constexpr int RA = (FROWS * (G::LWU / 4) + kWaveThreads - 1) / kWaveThreads;
-  using ReadAhead = TileReadAhead<kWaveThreads, RA>;
+  using ReadAhead = TileReadAhead<kWaveThreads, FROWS, G::LWU>;  // one staged tile read ahead
 };
 // dynamic LDS of the wide layout: cos/sin(pi m / T) [2T x 8 B], then the four
 // tables at kWideSpan strides
@@ -365,7 +363,7 @@ __device__ __forceinline__ void wave_tile_wide(const JobDesc& job, int X0, int Y
     v = fminf(fmaxf(v, 0.f), (float)F);  // NaN -> 0; the flag promises integers in [0, F]
     ftile[r][c] = tb + (uint32_t)((int)v * MODB);
   };
-  if (ra.valid) ra.commit(FROWS, LWU, put);
+  if (ra.valid) ra.commit(put);
   else stage_tile<kWaveThreads>(src, sp, FROWS, LWU, Y0 - W, X0 - Wal, H, Wd, put);
   __syncthreads();
 
@@ -571,9 +569,8 @@ __device__ __forceinline__ void wave_tile_wide(const JobDesc& job, int X0, int Y
   // committed are not kept across the next tile)
   {
     const int nWal = next ? (next->W + 7) & ~7 : 0;
-    ra.valid = next && WideLds<PREC, NT, TH>::ReadAhead::eligible(next->src, next->src_pitch, FROWS, LWU, nX0 - nWal,
-                                                                  next->width);
-    if (ra.valid) ra.issue(next->src, next->src_pitch, FROWS, LWU, nY0 - next->W, nX0 - nWal, next->height);
+    ra.valid = next && WideLds<PREC, NT, TH>::ReadAhead::eligible(next->src, next->src_pitch, nX0 - nWal, next->width);
+    if (ra.valid) ra.issue(next->src, next->src_pitch, nY0 - next->W, nX0 - nWal, next->height);
     else ra.clear();
   }
 
