@@ -4,7 +4,13 @@
 // neighbour of p is itself a pixel at most as far from p as the unfolded
 // offset, so the folded window adds no new pairs and the value equals
 //   max_p ( M(p) - f(p) ),  M = maximum of f over the window clipped to the image,
-// which needs only a separable maximum filter.  Three launches:
+// which needs only a separable maximum filter.  Each 1-D running maximum is
+// van Herk / Gil-Werman's: the staged line is cut into blocks of w = 2W + 1
+// samples from its first staged sample, and within each block a prefix
+// maximum g and a suffix maximum h are formed; a window [a, b] of at most w
+// samples then has maximum max(h[a], g[b]) when a and b lie in different
+// blocks, g[b] when a starts their common block and h[a] otherwise (b then
+// ends the staged line), so each output costs O(1) whatever W.  Three launches:
 //   1. rows:    R(y, x) = max f(y, x') over |x' - x| <= W (clipped), one
 //               workgroup per row segment, the segment staged in LDS;
 //   2. columns: M(y, x) = max R(y', x) over |y' - y| <= W (clipped) from an
@@ -21,44 +27,79 @@ namespace bf {
 namespace {
 
 constexpr int kRowSeg = 256;          // outputs per row workgroup
-constexpr int kColW = 64;             // columns per column workgroup
+constexpr int kColW = 32;             // columns per column workgroup
 constexpr int kColH = 64;             // output rows per column workgroup
-constexpr int kColThreads = 256;      // 64 columns x 4 row groups
+constexpr int kColThreads = 256;      // 32 columns x 8 row groups
+
+// Suffix (h) and prefix maxima of v[0..n) within blocks of w samples
+// starting at 0, one block per thread at a time; the prefix maxima overwrite
+// v (g = v on return); element i of a line is at stride `st` (1 along a row,
+// the tile width down a column).
+__device__ __forceinline__ void block_scans(float* v, float* h, int n, int w, int st, int lane0, int nlanes) {
+  const int nb = (n + w - 1) / w;
+  for (int bk = lane0; bk < nb; bk += nlanes) {
+    const int s0 = bk * w, s1 = min(s0 + w, n);
+    float m = v[(s1 - 1) * st];
+    h[(s1 - 1) * st] = m;
+    for (int i = s1 - 2; i >= s0; --i) {
+      m = fmaxf(m, v[i * st]);
+      h[i * st] = m;
+    }
+    m = v[s0 * st];
+    for (int i = s0 + 1; i < s1; ++i) {
+      m = fmaxf(m, v[i * st]);
+      v[i * st] = m;
+    }
+  }
+}
+
+// maximum over staged samples [a, b] (b - a < w) from the block maxima
+__device__ __forceinline__ float window_max(const float* g, const float* h, int a, int b, int w, int st) {
+  const int ba = a / w, bb = b / w;
+  if (ba != bb) return fmaxf(h[a * st], g[b * st]);
+  return (a == ba * w) ? g[b * st] : h[a * st];
+}
 
 __global__ void __launch_bounds__(kRowSeg) row_max_kernel(const float* __restrict__ src, int H, int Wd, int pitch,
                                                           int W, float* __restrict__ rmax) {
-  __shared__ float seg[kRowSeg + 2 * BF_MAX_W];
+  __shared__ float seg[kRowSeg + 2 * BF_MAX_W];  // the segment, then its prefix maxima
+  __shared__ float hs[kRowSeg + 2 * BF_MAX_W];
   const int y = blockIdx.y;
   const int x0 = blockIdx.x * kRowSeg;
   const int lo = max(x0 - W, 0), hi = min(x0 + kRowSeg + W, Wd);  // staged [lo, hi)
+  const int w = 2 * W + 1;
   for (int x = lo + (int)threadIdx.x; x < hi; x += kRowSeg) seg[x - lo] = src[(size_t)y * pitch + x];
+  __syncthreads();
+  block_scans(seg, hs, hi - lo, w, 1, (int)threadIdx.x, kRowSeg);
   __syncthreads();
   const int x = x0 + (int)threadIdx.x;
   if (x >= Wd) return;
   const int a = max(x - W, 0), b = min(x + W, Wd - 1);
-  float m = seg[a - lo];
-  for (int t = a + 1; t <= b; ++t) m = fmaxf(m, seg[t - lo]);
-  rmax[(size_t)y * Wd + x] = m;
+  rmax[(size_t)y * Wd + x] = window_max(seg, hs, a - lo, b - lo, w, 1);
 }
 
 __global__ void __launch_bounds__(kColThreads) col_max_kernel(const float* __restrict__ src, int H, int Wd,
                                                               int pitch, int W, const float* __restrict__ rmax,
                                                               float* __restrict__ block_max) {
-  extern __shared__ float tile[];  // [(kColH + 2W) rows][kColW]
+  extern __shared__ float tile[];  // two arrays of [(kColH + 2W) rows][kColW]: R (then its prefix maxima), suffix maxima
   __shared__ float red[kColThreads];
   const int x0 = blockIdx.x * kColW, y0 = blockIdx.y * kColH;
   const int r_lo = max(y0 - W, 0), r_hi = min(y0 + kColH + W, H);
-  const int c = threadIdx.x & (kColW - 1), g = threadIdx.x / kColW;
+  const int nr = r_hi - r_lo, w = 2 * W + 1;
+  float* ht = tile + (size_t)(kColH + 2 * W) * kColW;
+  const int c = threadIdx.x & (kColW - 1), grp = threadIdx.x / kColW;
   const int x = x0 + c;
-  for (int r = r_lo + g; r < r_hi; r += kColThreads / kColW)
+  for (int r = r_lo + grp; r < r_hi; r += kColThreads / kColW)
     tile[(r - r_lo) * kColW + c] = (x < Wd) ? rmax[(size_t)r * Wd + x] : 0.f;
+  __syncthreads();
+  // the row groups share a column's blocks
+  block_scans(tile + c, ht + c, nr, w, kColW, grp, kColThreads / kColW);
   __syncthreads();
   float best = 0.f;
   if (x < Wd) {
-    for (int y = y0 + g; y < min(y0 + kColH, H); y += kColThreads / kColW) {
+    for (int y = y0 + grp; y < min(y0 + kColH, H); y += kColThreads / kColW) {
       const int a = max(y - W, 0), b = min(y + W, H - 1);
-      float m = tile[(a - r_lo) * kColW + c];
-      for (int t = a + 1; t <= b; ++t) m = fmaxf(m, tile[(t - r_lo) * kColW + c]);
+      const float m = window_max(tile + c, ht + c, a - r_lo, b - r_lo, w, kColW);
       best = fmaxf(best, m - src[(size_t)y * pitch + x]);
     }
   }
@@ -120,7 +161,7 @@ extern "C" int bf_dynamic_range(const float* src, int height, int width, int src
   const dim3 g1((width + kRowSeg - 1) / kRowSeg, height);
   hipLaunchKernelGGL(row_max_kernel, g1, dim3(kRowSeg), 0, stream, src, height, width, src_pitch, W, rmax);
   const dim3 g2((width + kColW - 1) / kColW, (height + kColH - 1) / kColH);
-  const size_t lds = sizeof(float) * (size_t)(kColH + 2 * W) * kColW;
+  const size_t lds = 2 * sizeof(float) * (size_t)(kColH + 2 * W) * kColW;
   hipLaunchKernelGGL(col_max_kernel, g2, dim3(kColThreads), lds, stream, src, height, width, src_pitch, W, rmax,
                      bmax);
   const int nb = static_cast<int>(n_col_blocks(height, width));
