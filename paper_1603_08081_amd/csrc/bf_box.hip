@@ -12,7 +12,7 @@
 // stays as close to the FP64 eq. (9) as the float32 MFMA path while doing
 // O(1) work per plane and pixel instead of O(W).
 //
-// Tile: 64 output columns x 64 output rows per workgroup of 256 threads,
+// Tile: 64 output columns x 64 output rows per workgroup of 512 threads,
 // W <= 24.  LDS: the staged gray levels (16-bit) of the haloed tile, the row
 // sums of the tile's 64 + 2W rows (float4 per column), and (dynamic) the
 // per-harmonic table and the cos/sin(pi m / T) table.
@@ -23,7 +23,7 @@ namespace box_detail {
 
 using namespace fused_detail;
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;
 constexpr int kCols = 64;   // output columns per tile
 constexpr int kRows = 64;   // output rows per tile
 constexpr int kMaxW = 24;
@@ -64,13 +64,14 @@ __device__ __forceinline__ void box_tile(const JobDesc& job, int X0, int Y0, uns
     ft[r][c] = (uint16_t)(int)v;
   });
 
-  // row-sum thread: row hr, 32-column half hs; column-sum thread: column vx,
-  // 16-row quarter vq
-  const int hr = tid >> 1, hs = tid & 1;
+  // row-sum thread: row hr, 16-column quarter hs; column-sum thread: column
+  // vx, 8-row eighth vq
+  constexpr int kSegC = kCols / 4, kSegR = kRows / 8;
+  const int hr = tid >> 2, hs = tid & 3;
   const int vx = tid & 63, vq = tid >> 6;
-  double P[16], Q[16];
+  double P[kSegR], Q[kSegR];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) P[i] = Q[i] = 0.0;
+  for (int i = 0; i < kSegR; ++i) P[i] = Q[i] = 0.0;
   const PhaseTab pt{lut, 2.f * (float)T, 1.f / (2.f * (float)T), 1.f / (float)T, 2 * T};
 
   for (int k = 0; k <= K; ++k) {
@@ -85,7 +86,7 @@ __device__ __forceinline__ void box_tile(const JobDesc& job, int X0, int Y0, uns
     // ---- row sums: H[r][x] = sum over tile columns x .. x + 2W of row r.
     // Loads run in chunks of 8 ahead of the (serial) running sum.
     if (hr < R) {
-      const int x0 = 32 * hs;
+      const int x0 = kSegC * hs;
       double4 a = make_double4(0.0, 0.0, 0.0, 0.0), b = a;
       for (int c = x0; c <= x0 + 2 * W; c += 8) {
         float4 e[8];
@@ -100,17 +101,17 @@ __device__ __forceinline__ void box_tile(const JobDesc& job, int X0, int Y0, uns
       }
       a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w;
       H[hr][x0] = make_float4((float)a.x, (float)a.y, (float)a.z, (float)a.w);
-      for (int x = x0 + 1; x < x0 + 32; x += 8) {
+      for (int x = x0 + 1; x < x0 + kSegC; x += 8) {
         float4 ein[8], eout[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          const int xu = min(x + u, x0 + 31);
+          const int xu = min(x + u, x0 + kSegC - 1);
           ein[u] = tab[ft[hr][xu + 2 * W]];
           eout[u] = tab[ft[hr][xu - 1]];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          if (x + u >= x0 + 32) break;
+          if (x + u >= x0 + kSegC) break;
           a.x += (double)ein[u].x - (double)eout[u].x;
           a.y += (double)ein[u].y - (double)eout[u].y;
           a.z += (double)ein[u].z - (double)eout[u].z;
@@ -120,9 +121,9 @@ __device__ __forceinline__ void box_tile(const JobDesc& job, int X0, int Y0, uns
       }
     }
     __syncthreads();
-    // ---- column sums down column vx, demodulation at 16 output rows
+    // ---- column sums down column vx, demodulation at kSegR output rows
     {
-      const int y0 = 16 * vq;
+      const int y0 = kSegR * vq;
       double4 a = make_double4(0.0, 0.0, 0.0, 0.0), b = a;
       for (int r = y0; r <= y0 + 2 * W; r += 8) {
         float4 e[8];
@@ -138,14 +139,14 @@ __device__ __forceinline__ void box_tile(const JobDesc& job, int X0, int Y0, uns
       a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w;
       const double dk = job.d[k];
 #pragma unroll
-      for (int i0 = 0; i0 < 16; i0 += 8) {
+      for (int i0 = 0; i0 < kSegR; i0 += 8) {
         float2 cs[8];
         float4 ein[8], eout[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const float4 t = tab[ft[y0 + i0 + u + W][vx + W]];
           cs[u] = make_float2(t.x, t.y);
-          const int iu = min(i0 + u, 14);
+          const int iu = min(i0 + u, kSegR - 2);
           ein[u] = H[y0 + iu + 2 * W + 1][vx];
           eout[u] = H[y0 + iu][vx];
         }
@@ -155,7 +156,7 @@ __device__ __forceinline__ void box_tile(const JobDesc& job, int X0, int Y0, uns
           const double dc = dk * (double)cs[u].x, ds = dk * (double)cs[u].y;
           Q[i] = fma(dc, a.x, fma(ds, a.y, Q[i]));
           P[i] = fma(dc, a.z, fma(ds, a.w, P[i]));
-          if (i < 15) {
+          if (i < kSegR - 1) {
             a.x += (double)ein[u].x - (double)eout[u].x;
             a.y += (double)ein[u].y - (double)eout[u].y;
             a.z += (double)ein[u].z - (double)eout[u].z;
@@ -173,15 +174,15 @@ __device__ __forceinline__ void box_tile(const JobDesc& job, int X0, int Y0, uns
   const int xo = X0 + vx;
   unsigned flags = 0;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int yo = Y0 + 16 * vq + i;
+  for (int i = 0; i < kSegR; ++i) {
+    const int yo = Y0 + kSegR * vq + i;
     if (yo < H_img && xo < W_img) {
       job.dst[(size_t)yo * job.dst_pitch + xo] = (float)(P[i] / Q[i] + (double)c0);
       if (!(Q[i] >= tau)) flags |= 1u << i;
     }
   }
   refine_pooled(flags != 0, [&](auto&& emit) {
-    for (unsigned m = flags; m; m &= m - 1) emit(16 * vq + __ffs(m) - 1, vx);
+    for (unsigned m = flags; m; m &= m - 1) emit(kSegR * vq + __ffs(m) - 1, vx);
   }, job, X0, Y0, W, w1s, lut, reinterpret_cast<unsigned char*>(tab), 16 * (size_t)(F + 1), kThreads,
   [&](int r, int c) { return (int)ft[r][c]; });
   __syncthreads();  // the LDS of this tile may be reused by the caller
