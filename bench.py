@@ -78,7 +78,7 @@ def issued_flops_per_px(K, W, tile_rows):
 
 
 # standalone HIP units that share no code with the filter kernels measured here
-_OTHER_UNITS = ("bf_range.hip", "bf_recursive.hip")
+_OTHER_UNITS = ("bf_box.hip", "bf_noalloc.hip", "bf_range.hip", "bf_recursive.hip")
 
 
 def kernel_sources_digest():
