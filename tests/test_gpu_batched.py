@@ -9,6 +9,9 @@
 - Plans: eager launch and HIP-graph replay equal bf_filter_batched, on every
   replay, with other device work between replays and new input written into
   the same buffers.
+- Pitched and misaligned input and output views (row pitch a multiple of 4
+  or odd, start 16-byte aligned or not), mixed in one batch: the bits of the
+  single-image call on contiguous tensors, nothing written outside the views.
 - The mixed 64-image workload (sizes 256..4096 per side, W 6..48, K up to 40,
   Gaussian and exponential range kernels) in FP32 planes against the FP64
   oracle of eq. (9) on sampled rows of every image.
@@ -218,6 +221,66 @@ def test_plan_on_side_stream_and_reupload():
     for a, b in zip(ref, out):
         assert torch.equal(a, b)
     plan.destroy()
+
+
+def _laid_out(torch, f, layout, fill):
+    """A CUDA view holding f with the given row pitch and start alignment;
+    the elements outside the view hold `fill` (a valid gray level different
+    from the image's content, so a read past the row end changes the
+    result)."""
+    h, w = f.shape
+    lead, pitch = {"contig": (0, w),
+                   "pitch4": (0, (w + 7) // 4 * 4),       # 16-byte rows, aligned start
+                   "offset1": (1, (w + 8) // 4 * 4),      # 16-byte rows, start 4 bytes past alignment
+                   "odd": (2, w + 3 if w % 2 == 0 else w + 4)}[layout]  # odd pitch
+    base = torch.full((h, pitch), float(fill), dtype=torch.float32, device="cuda")
+    view = base[:, lead:lead + w]
+    view.copy_(torch.from_numpy(f).cuda())
+    assert view.stride(-2) == pitch
+    return base, view
+
+
+@pytest.mark.parametrize("prec", ["fp16", "fp32"])
+@pytest.mark.parametrize("grid", ["", "3"])
+def test_pitched_and_misaligned_layouts_match_contiguous(prec, grid, monkeypatch):
+    """Row pitch and start alignment only change how a tile is read (whole
+    16-byte rows when the rows and the tile start are 16-byte aligned,
+    otherwise element by element; the persistent 16-bit kernel also reads a
+    tile ahead only when the next one is aligned): on pitched input and output
+    views, jobs of mixed layouts in one batch give the bits of the
+    single-image call on contiguous tensors, and nothing outside the output
+    views is written.  Grid "3" makes each workgroup walk tiles of several
+    jobs whose layouts alternate."""
+    torch = _torch()
+    from paper_1603_08081_amd import native
+    specs = _mixed_specs() + [
+        dict(h=200, w=256, spatial="gaussian", sigma_s=8.0, W=24, rk="gaussian", sr=15.0, T=255, eps=0.0,
+             K_max=32, integer=True),
+        dict(h=161, w=384, spatial="gaussian", sigma_s=4.0, W=12, rk="gaussian", sr=20.0, T=255, eps=1e-3,
+             integer=True)]
+    imgs = _inputs(specs)
+    stream = torch.cuda.current_stream()
+    srcs = [torch.from_numpy(f).cuda() for f in imgs]
+    ref = [torch.full_like(x, -1.0) for x in srcs]
+    for j in _jobs(native, specs, srcs, ref):
+        native.bf_filter(j, prec, stream=stream)
+    layouts = ("pitch4", "offset1", "odd", "contig")
+    views, bases, obases, outs = [], [], [], []
+    for i, (s, f) in enumerate(zip(specs, imgs)):
+        b, v = _laid_out(torch, f, layouts[i % 4], s["T"])
+        ob, ov = _laid_out(torch, np.full_like(f, -1.0), layouts[(i + 1) % 4], -5.0)
+        bases.append(b), views.append(v), obases.append(ob), outs.append(ov)
+    monkeypatch.setenv("BF_BATCH_GRID", grid)
+    ws, st = _batched(native, torch, _jobs(native, specs, views, outs), prec, stream)
+    torch.cuda.synchronize()
+    assert st in (native.BF_OK, native.BF_FIT_NOT_CONVERGED)
+    for i, (a, b) in enumerate(zip(ref, outs)):
+        lay = (layouts[i % 4], layouts[(i + 1) % 4])
+        assert torch.isfinite(b).all(), "job %d %s" % (i, lay)
+        assert torch.equal(a, b), "job %d in/out layouts %s" % (i, lay)
+        mask = torch.ones_like(obases[i], dtype=torch.bool)
+        mask[:, b.storage_offset():b.storage_offset() + b.shape[1]] = False
+        assert (obases[i][mask] == -5.0).all(), "job %d wrote outside its output view" % i
 
 
 @pytest.fixture(scope="module")
