@@ -205,10 +205,11 @@ def recursive_bytes_per_px(K):
     """Bytes per pixel the recursive-Gaussian path moves to and from memory
     (before caches), per harmonic: the row pass reads f in both directions and
     writes, re-reads and rewrites four float32 planes (56); the column pass
-    reads them and f in both directions, writes two float64 shares on the way
-    down and reads and rewrites them on the way up (88); the final sum reads
-    the shares (16).  Plus the output."""
-    return (K + 1) * (56 + 88 + 16) + 4
+    reads them in both directions, and f in both directions for each of the
+    numerator and denominator shares, writes the two float64 shares on the
+    way down and reads and rewrites them on the way up (96); the final sum
+    reads the shares (16).  Plus the output."""
+    return (K + 1) * (56 + 96 + 16) + 4
 
 
 def run_recursive(args):

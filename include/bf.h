@@ -329,11 +329,14 @@ int bf_dynamic_range(const float* src, int height, int width, int src_pitch, int
  * result differs from bf_filter's truncated Gaussian of eq. (2) by the
  * difference of the two spatial kernels (a variant, not the same filter).
  *   job         as for bf_filter, except: spatial must be BF_SPATIAL_GAUSSIAN,
- *               0 < sigma_s <= 256, W is not used; with
- *               BF_FLAG_INTEGER_INPUT the row pass takes cos and sin of
- *               k w f from a float32 table of pi m / T, m = k f mod 2T
- *               (same contract as for bf_filter), otherwise phases are
- *               computed per pixel in float64
+ *               0 < sigma_s <= 256, W is not used, height x max(src_pitch,
+ *               width) below 2^28 elements (BF_E_UNSUPPORTED otherwise);
+ *               with BF_FLAG_INTEGER_INPUT the row pass takes cos and sin of
+ *               k w f from a float32 table of pi m / T, m = k f mod 2T, and
+ *               the column pass from a float64 one (same contract as for
+ *               bf_filter: pixels are gray levels 0..f_max, others are
+ *               clamped into that range), otherwise phases are computed per
+ *               pixel in float64
  *   workspace   device memory of at least bf_recursive_workspace_bytes(job)
  *               bytes (32 (K + 1) per pixel: the float32 row-smoothed planes
  *               of every harmonic and each harmonic's float64 shares of

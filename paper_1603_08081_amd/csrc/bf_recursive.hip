@@ -1,19 +1,20 @@
 // Eq. (9) with the spatial convolutions of Algorithm 1 done by Deriche's
 // recursive Gaussian, the constant-time smoothing Sec. 2 cites.  Three
 // launches, the harmonics k = 0..K side by side in the grid (blockIdx.y):
-//   1. rows:    one lane per (image row, k), 64 rows staged through LDS
-//               together, modulates f into the four planes
+//   1. rows:    one lane per (image row, k, plane), 64 rows staged through
+//               LDS together, modulates f into its plane of
 //               (f - c0) cos, (f - c0) sin, cos, sin of k w f (w = pi / T,
 //               c0 the centre of the gray-level range) and runs the
 //               causal and anti-causal fourth-order recursions over the row
 //               (half-sample symmetric extension), writing the row-smoothed
 //               planes of harmonic k;
-//   2. columns: one lane per (image column, k) runs the same recursions down
-//               the row-smoothed planes and demodulates with d_k: harmonic k's
-//               share of the numerator, cos S((f - c0) cos) + sin S((f - c0) sin), and of
-//               the denominator, cos S(cos) + sin S(sin), times d_k (the
-//               causal and anti-causal halves of S demodulated one after the
-//               other into the same shares);
+//   2. columns: one lane per (image column, k, share) runs the same
+//               recursions down two row-smoothed planes and demodulates with
+//               d_k: harmonic k's share of the numerator,
+//               cos S((f - c0) cos) + sin S((f - c0) sin), or of the
+//               denominator, cos S(cos) + sin S(sin), times d_k (the causal
+//               and anti-causal halves of S demodulated one after the other
+//               into the same share);
 //   3. one lane per pixel sums the K + 1 shares in float64, divides and adds c0.
 // The recursions' state is float64; so are the phases: computed per pixel,
 // or for integer images looked up in a table of cos and sin of pi m / T
@@ -31,6 +32,7 @@
 // (n >= 1, run backwards) has numerator N(z) - g(0) D(z).  Scaled to unit sum.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -45,6 +47,9 @@ constexpr int kLineThreads = 64;     // one wavefront of lines per workgroup
 // Above this the poles of the fourth-order recursion come so close to 1 that
 // its float64 rounding reaches 1e-5 of the signal per pass.
 constexpr double kMaxSigmaRec = 256.0;
+// Images (rows x row pitch) below this many elements: the kernels' byte
+// offsets of float64 shares then fit in 32 bits.
+constexpr size_t kMaxRecElems = (size_t)1 << 28;
 
 struct RecCoef {
   double nc[4];   // causal numerator, x(i) .. x(i - 3)
@@ -59,7 +64,8 @@ struct RecArgs {
   int height, width, src_pitch, dst_pitch;
   int T;
   int K;
-  int integer;     // BF_FLAG_INTEGER_INPUT: phases of the row pass from a table
+  int integer;     // BF_FLAG_INTEGER_INPUT: phases from tables of cos/sin(pi m / T)
+  int F;           // integer images: gray levels 0..F
   float c0;        // centre of the gray-level range
   RecCoef c;
   float* rows;     // [K + 1][4][height][width], row-smoothed planes
@@ -141,91 +147,133 @@ __device__ __forceinline__ void phase(float f, int k, int T, double* c, double* 
 }
 
 // The row pass goes through LDS in blocks of 64 rows x kChunk positions: the
-// wavefront loads and stores whole row segments (coalesced) while each lane
-// walks its own row inside the block.
+// workgroup loads and stores whole row segments (coalesced) while each lane
+// walks its own row inside the block.  The four planes of a row are four
+// independent recursions: wavefront p of the workgroup runs plane p of the
+// block's 64 rows, so that four times as many wavefronts share the work of a
+// harmonic (one lane's recursion is a long dependent chain; more wavefronts
+// per SIMD hide more of its latency) and the block's f is staged once for
+// all four.
 constexpr int kChunk = 16;
 constexpr int kTileStride = kChunk + 1;   // odd stride: a lane per row hits distinct banks
-constexpr int kRowsPerPass = kLineThreads / kChunk;   // rows one block transfer instruction covers
-constexpr int kBlockRows = kLineThreads / kRowsPerPass;  // block transfer instructions per lane
-static_assert(kLineThreads % kChunk == 0, "block transfers split the wavefront into whole row segments");
+constexpr int kRowThreads = 4 * kLineThreads;           // a wavefront per plane
+constexpr int kRowsPerPass = kRowThreads / kChunk;      // rows one block transfer instruction covers
+constexpr int kBlockRows = kLineThreads / kRowsPerPass;  // f transfers per thread and block
+static_assert(kRowThreads % kChunk == 0 && kLineThreads % kRowsPerPass == 0,
+              "block transfers split the workgroup into whole row segments");
 
-// cos and sin of pi m / T for m = k f mod 2T, f an integer gray level; the
-// index is reduced into [0, 2T) whatever f holds
-__device__ __forceinline__ float2 phase_tab(const float2* tab, float f, int k, int T) {
-  const int T2 = 2 * T;
-  const float fc = fminf(fmaxf(f, 0.0f), 1.0e6f);
-  int m = static_cast<int>((static_cast<long long>(k) * static_cast<long long>(fc)) % T2);
-  return tab[m];
+// m = k f mod 2T for an integer image: f clamped to the gray levels 0..F the
+// integer flag promises (k f < 2^18 then, exact in float32); the quotient
+// estimate in float32 is off by at most one, which the two corrections take
+// back, so m is exact and always in [0, 2T)
+__device__ __forceinline__ int phase_index(float f, int k, int T2, float inv_t2, float fmax) {
+  const int kf = k * static_cast<int>(fminf(fmaxf(f, 0.0f), fmax));
+  int m = kf - T2 * static_cast<int>(static_cast<float>(kf) * inv_t2);
+  m += m < 0 ? T2 : 0;
+  m -= m >= T2 ? T2 : 0;
+  return m;
 }
 
-__global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a) {
+// a float at a wave-uniform base plus a 32-bit byte offset: the global
+// access takes the base in scalar registers and one vector register for the
+// offset (the host keeps images below 2^28 elements, so that every offset of
+// the recursive path fits)
+__device__ __forceinline__ float ld_at(const float* base, uint32_t byte_off) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+__device__ __forceinline__ void st_at(float* base, uint32_t byte_off, float v) {
+  *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+__device__ __forceinline__ double ld_at(const double* base, uint32_t byte_off) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+__device__ __forceinline__ void st_at(double* base, uint32_t byte_off, double v) {
+  *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
+__global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) {
   __shared__ float ft[kLineThreads * kTileStride];       // f of the block
   __shared__ float ot[4 * kLineThreads * kTileStride];   // the four planes of the block
   extern __shared__ float2 cs_tab[];                     // 2T entries (cos, sin) when a.integer
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
+  // the plane this wavefront runs (wave-uniform), and the lane's row
+  const int pl = __builtin_amdgcn_readfirstlane(tid / kLineThreads);
+  const int lane = tid % kLineThreads;
   const int y0 = blockIdx.x * kLineThreads;
   const int k = blockIdx.y;
   const int L = a.width, M = a.c.margin;
   const int nrows = min(kLineThreads, a.height - y0);
   const size_t plane = (size_t)a.height * a.width;
   float* outk = a.rows + 4 * plane * k;
-  // in block transfers lane = (row offset r0, position q)
-  const int q = lane % kChunk, r0 = lane / kChunk;
+  // in block transfers thread = (row offset r0, position q)
+  const int q = tid % kChunk, r0 = tid / kChunk;
   const double c0 = a.c0;
   if (a.integer) {
-    for (int m = lane; m < 2 * a.T; m += kLineThreads) {
+    for (int m = tid; m < 2 * a.T; m += kRowThreads) {
       double c, s;
       sincospi(static_cast<double>(m) / a.T, &s, &c);
       cs_tab[m] = make_float2(static_cast<float>(c), static_cast<float>(s));
     }
   }
   __syncthreads();
+  const int T2 = 2 * a.T;
+  const float inv_t2 = 1.0f / static_cast<float>(T2), fmax = static_cast<float>(a.F);
+  // this wavefront's plane of the modulated signal at gray level f
+  auto modulated = [&](float f) -> double {
+    double c, s;
+    if (a.integer) {
+      const float2 cs = cs_tab[phase_index(f, k, T2, inv_t2, fmax)];
+      c = cs.x;
+      s = cs.y;
+    } else {
+      phase(f, k, a.T, &c, &s);
+    }
+    const double fc = (double)f - c0;
+    return pl == 0 ? fc * c : pl == 1 ? fc * s : pl == 2 ? c : s;
+  };
+  float* const myot = ot + (size_t)pl * kLineThreads * kTileStride + lane * kTileStride;
+  // Each pass reads block b + 1 into registers while it runs block b, and
+  // needs two barriers per block: the one after staging (the block is in
+  // LDS) and the one after the recursions (the planes are in LDS); the copy
+  // of the planes out and the staging of the next block, both before the
+  // next first barrier, touch no LDS that a recursion of the other block uses.
+  //
   // causal pass over positions -M .. L - 1
-  double xh[4][4] = {};  // x(i), x(i-1), x(i-2), x(i-3) per plane
-  double yh[4][4] = {};  // y(i-1) .. y(i-4)
+  float fv[kBlockRows];  // f of the next block (column fold(i0 + q))
+  auto read_f = [&](int i0) {
+    const int col = fold(i0 + q, L);
+    const bool inb = q < min(kChunk, L - i0);
+#pragma unroll
+    for (int t = 0; t < kBlockRows; ++t) {
+      const int r = r0 + t * kRowsPerPass;
+      fv[t] = (inb && r < nrows) ? ld_at(a.src, 4u * (uint32_t)((y0 + r) * a.src_pitch + col)) : 0.f;
+    }
+  };
+  double xh[4] = {};  // x(i), x(i-1), x(i-2), x(i-3)
+  double yh[4] = {};  // y(i-1) .. y(i-4)
+  read_f(-M);
   for (int i0 = -M; i0 < L; i0 += kChunk) {
     const int n = min(kChunk, L - i0);
     if (q < n) {
-      const int col = fold(i0 + q, L);
-      float v[kBlockRows];
-#pragma unroll
-      for (int t = 0; t < kBlockRows; ++t) {
-        const int r = r0 + t * kRowsPerPass;
-        v[t] = r < nrows ? a.src[(size_t)(y0 + r) * a.src_pitch + col] : 0.f;
-      }
 #pragma unroll
       for (int t = 0; t < kBlockRows; ++t)
-        if (r0 + t * kRowsPerPass < nrows) ft[(r0 + t * kRowsPerPass) * kTileStride + q] = v[t];
+        if (r0 + t * kRowsPerPass < nrows) ft[(r0 + t * kRowsPerPass) * kTileStride + q] = fv[t];
     }
     __syncthreads();
+    if (i0 + kChunk < L) read_f(i0 + kChunk);
     if (lane < nrows) {
       for (int j = 0; j < n; ++j) {
-        const float f = ft[lane * kTileStride + j];
-        double c, s;
-        if (a.integer) {
-          const float2 cs = phase_tab(cs_tab, f, k, a.T);
-          c = cs.x;
-          s = cs.y;
-        } else {
-          phase(f, k, a.T, &c, &s);
-        }
-        const double fc = (double)f - c0;
-        const double x[4] = {fc * c, fc * s, c, s};
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          xh[p][3] = xh[p][2];
-          xh[p][2] = xh[p][1];
-          xh[p][1] = xh[p][0];
-          xh[p][0] = x[p];
-          const double v = a.c.nc[0] * xh[p][0] + a.c.nc[1] * xh[p][1] + a.c.nc[2] * xh[p][2] +
-                           a.c.nc[3] * xh[p][3] - a.c.dd[1] * yh[p][0] - a.c.dd[2] * yh[p][1] -
-                           a.c.dd[3] * yh[p][2] - a.c.dd[4] * yh[p][3];
-          yh[p][3] = yh[p][2];
-          yh[p][2] = yh[p][1];
-          yh[p][1] = yh[p][0];
-          yh[p][0] = v;
-          ot[(p * kLineThreads + lane) * kTileStride + j] = static_cast<float>(v);
-        }
+        xh[3] = xh[2];
+        xh[2] = xh[1];
+        xh[1] = xh[0];
+        xh[0] = modulated(ft[lane * kTileStride + j]);
+        const double v = a.c.nc[0] * xh[0] + a.c.nc[1] * xh[1] + a.c.nc[2] * xh[2] + a.c.nc[3] * xh[3] -
+                         a.c.dd[1] * yh[0] - a.c.dd[2] * yh[1] - a.c.dd[3] * yh[2] - a.c.dd[4] * yh[3];
+        yh[3] = yh[2];
+        yh[2] = yh[1];
+        yh[1] = yh[0];
+        yh[0] = v;
+        myot[j] = static_cast<float>(v);
       }
     }
     __syncthreads();
@@ -233,78 +281,63 @@ __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a)
       for (int r = r0; r < nrows; r += kRowsPerPass)
 #pragma unroll
         for (int p = 0; p < 4; ++p)
-          outk[p * plane + (size_t)(y0 + r) * L + i0 + q] = ot[(p * kLineThreads + r) * kTileStride + q];
+          st_at(outk + p * plane, 4u * (uint32_t)((y0 + r) * L + i0 + q), ot[(p * kLineThreads + r) * kTileStride + q]);
     }
-    __syncthreads();
   }
   // anti-causal pass over positions L - 1 + M .. 0, blocks [lo, hi] from the top
-  double xa[4][4] = {};  // x(i+1) .. x(i+4)
-  double ya[4][4] = {};  // y(i+1) .. y(i+4)
+  float ov[4][kBlockRows];  // causal halves of the next block
+  auto read_block = [&](int hi) {
+    const int lo = max(hi - kChunk + 1, 0);
+    const int i = lo + q;
+    const int col = fold(i, L);
+    const bool inb = q <= hi - lo;
+#pragma unroll
+    for (int t = 0; t < kBlockRows; ++t) {
+      const int r = r0 + t * kRowsPerPass;
+      const bool ok = inb && r < nrows;
+      fv[t] = ok ? ld_at(a.src, 4u * (uint32_t)((y0 + r) * a.src_pitch + col)) : 0.f;
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        ov[p][t] = (ok && i < L) ? ld_at(outk + p * plane, 4u * (uint32_t)((y0 + r) * L + i)) : 0.f;
+    }
+  };
+  __syncthreads();  // the last causal block's planes are out of LDS
+  double xa[4] = {};  // x(i+1) .. x(i+4)
+  double ya[4] = {};  // y(i+1) .. y(i+4)
+  read_block(L - 1 + M);
   for (int hi = L - 1 + M; hi >= 0; hi -= kChunk) {
     const int lo = max(hi - kChunk + 1, 0);
     const int n = hi - lo + 1;
     if (q < n) {
       const int i = lo + q;
-      const int col = fold(i, L);
-      // the block's f and causal halves, read in two batches of half the rows
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        constexpr int HB = kBlockRows / 2;
-        float v[HB], o[4][HB];
+      for (int t = 0; t < kBlockRows; ++t) {
+        const int r = r0 + t * kRowsPerPass;
+        if (r < nrows) {
+          ft[r * kTileStride + q] = fv[t];
+          if (i < L) {
 #pragma unroll
-        for (int t = 0; t < HB; ++t) {
-          const int r = r0 + (h * HB + t) * kRowsPerPass;
-          const bool ok = r < nrows;
-          v[t] = ok ? a.src[(size_t)(y0 + r) * a.src_pitch + col] : 0.f;
-#pragma unroll
-          for (int p = 0; p < 4; ++p) o[p][t] = (ok && i < L) ? outk[p * plane + (size_t)(y0 + r) * L + i] : 0.f;
-        }
-#pragma unroll
-        for (int t = 0; t < HB; ++t) {
-          const int r = r0 + (h * HB + t) * kRowsPerPass;
-          if (r < nrows) {
-            ft[r * kTileStride + q] = v[t];
-            if (i < L) {
-#pragma unroll
-              for (int p = 0; p < 4; ++p) ot[(p * kLineThreads + r) * kTileStride + q] = o[p][t];
-            }
+            for (int p = 0; p < 4; ++p) ot[(p * kLineThreads + r) * kTileStride + q] = ov[p][t];
           }
         }
       }
     }
     __syncthreads();
+    if (hi - kChunk >= 0) read_block(hi - kChunk);
     if (lane < nrows) {
       for (int j = n - 1; j >= 0; --j) {
-        const float f = ft[lane * kTileStride + j];
-        double c, s;
-        if (a.integer) {
-          const float2 cs = phase_tab(cs_tab, f, k, a.T);
-          c = cs.x;
-          s = cs.y;
-        } else {
-          phase(f, k, a.T, &c, &s);
-        }
-        const double fc = (double)f - c0;
-        const double x[4] = {fc * c, fc * s, c, s};
-        const bool inside = lo + j < L;
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          const double v = a.c.na[1] * xa[p][0] + a.c.na[2] * xa[p][1] + a.c.na[3] * xa[p][2] +
-                           a.c.na[4] * xa[p][3] - a.c.dd[1] * ya[p][0] - a.c.dd[2] * ya[p][1] -
-                           a.c.dd[3] * ya[p][2] - a.c.dd[4] * ya[p][3];
-          ya[p][3] = ya[p][2];
-          ya[p][2] = ya[p][1];
-          ya[p][1] = ya[p][0];
-          ya[p][0] = v;
-          xa[p][3] = xa[p][2];
-          xa[p][2] = xa[p][1];
-          xa[p][1] = xa[p][0];
-          xa[p][0] = x[p];
-          if (inside) {
-            float& o = ot[(p * kLineThreads + lane) * kTileStride + j];
-            o = static_cast<float>(o + v);
-          }
-        }
+        const double x = modulated(ft[lane * kTileStride + j]);
+        const double v = a.c.na[1] * xa[0] + a.c.na[2] * xa[1] + a.c.na[3] * xa[2] + a.c.na[4] * xa[3] -
+                         a.c.dd[1] * ya[0] - a.c.dd[2] * ya[1] - a.c.dd[3] * ya[2] - a.c.dd[4] * ya[3];
+        ya[3] = ya[2];
+        ya[2] = ya[1];
+        ya[1] = ya[0];
+        ya[0] = v;
+        xa[3] = xa[2];
+        xa[2] = xa[1];
+        xa[1] = xa[0];
+        xa[0] = x;
+        if (lo + j < L) myot[j] = static_cast<float>(myot[j] + v);
       }
     }
     __syncthreads();
@@ -312,24 +345,27 @@ __global__ void __launch_bounds__(kLineThreads) rec_rows_kernel(const RecArgs a)
       for (int r = r0; r < nrows; r += kRowsPerPass)
 #pragma unroll
         for (int p = 0; p < 4; ++p)
-          outk[p * plane + (size_t)(y0 + r) * L + lo + q] = ot[(p * kLineThreads + r) * kTileStride + q];
+          st_at(outk + p * plane, 4u * (uint32_t)((y0 + r) * L + lo + q), ot[(p * kLineThreads + r) * kTileStride + q]);
     }
-    __syncthreads();
   }
 }
 
 // The column pass demodulates the causal and the anti-causal halves of each
 // smoothed plane separately (demodulation is linear): the causal sweep writes
 // harmonic k's shares of numerator and denominator from its half, and the
-// anti-causal sweep adds its own, so no causal half is stored.  Each sweep
-// reads kColAhead positions at a time before it runs their recursion steps.
-// For integer images the demodulation's cos and sin of pi m / T,
-// m = k f mod 2T, come from a float64 table in LDS built by the workgroup.
-constexpr int kColAhead = 8;
+// anti-causal sweep adds its own, so no causal half is stored.  The numerator
+// share needs planes 0 and 1 only, the denominator share planes 2 and 3:
+// blockIdx.z picks the pair, so that each lane runs two recursions and twice
+// as many wavefronts share the work.  Each sweep reads kColAhead positions at
+// a time, one batch ahead of the recursion steps.  For integer images the
+// demodulation's cos and sin of pi m / T, m = k f mod 2T, come from a float64
+// table in LDS built by the workgroup.
+constexpr int kColAhead = 4;
 __global__ void __launch_bounds__(kLineThreads) rec_cols_kernel(const RecArgs a) {
   extern __shared__ double2 dcs_tab[];  // 2T entries (cos, sin) when a.integer
   const int x0 = blockIdx.x * kLineThreads + threadIdx.x;
   const int k = blockIdx.y;
+  const int half = blockIdx.z;  // 0: numerator share (planes 0, 1); 1: denominator share (planes 2, 3)
   if (a.integer) {
     for (int m = threadIdx.x; m < 2 * a.T; m += kLineThreads) {
       double c, s;
@@ -339,13 +375,12 @@ __global__ void __launch_bounds__(kLineThreads) rec_cols_kernel(const RecArgs a)
     __syncthreads();
   }
   if (x0 >= a.width) return;
+  const int T2 = 2 * a.T;
+  const float inv_t2 = 1.0f / static_cast<float>(T2), fmax = static_cast<float>(a.F);
   // cos and sin of k pi f / T for this column's pixels
   auto demod_phase = [&](float f, double* c, double* s) {
     if (a.integer) {
-      const int T2 = 2 * a.T;
-      const float fc = fminf(fmaxf(f, 0.0f), 1.0e6f);
-      const int m = static_cast<int>((static_cast<long long>(k) * static_cast<long long>(fc)) % T2);
-      const double2 cs = dcs_tab[m];
+      const double2 cs = dcs_tab[phase_index(f, k, T2, inv_t2, fmax)];
       *c = cs.x;
       *s = cs.y;
     } else {
@@ -354,27 +389,45 @@ __global__ void __launch_bounds__(kLineThreads) rec_cols_kernel(const RecArgs a)
   };
   const int L = a.height, M = a.c.margin, Wd = a.width;
   const size_t plane = (size_t)a.height * a.width;
-  const float* in = a.rows + 4 * plane * k + x0;
+  // wave-uniform bases; lane offsets in bytes
+  const float* in0 = a.rows + (4 * (size_t)k + 2 * half) * plane;
+  const float* in1 = in0 + plane;
+  double* share = (half ? a.Q : a.P) + plane * k;
+  const uint32_t xo = static_cast<uint32_t>(x0);
   const double dk = a.d[k];
-  double xh[4][4] = {};
-  double yh[4][4] = {};
-  for (int i0 = -M; i0 < L; i0 += kColAhead) {
-    float xin[kColAhead][4], fs[kColAhead];
+  // the values of the next kColAhead positions are read while the current
+  // ones run their recursion steps
+  float nx[kColAhead][2], nf[kColAhead];
+  double ns[kColAhead];
+  auto read_down = [&](int i0) {
 #pragma unroll
     for (int j = 0; j < kColAhead; ++j) {
       const int i = i0 + j;
-      const size_t r = (size_t)fold(i, L) * Wd;
-#pragma unroll
-      for (int p = 0; p < 4; ++p) xin[j][p] = i < L ? in[p * plane + r] : 0.f;
-      fs[j] = (i >= 0 && i < L) ? a.src[(size_t)i * a.src_pitch + x0] : 0.f;
+      const uint32_t r = 4u * (static_cast<uint32_t>(fold(i, L) * Wd) + xo);
+      nx[j][0] = i < L ? ld_at(in0, r) : 0.f;
+      nx[j][1] = i < L ? ld_at(in1, r) : 0.f;
+      nf[j] = (i >= 0 && i < L) ? ld_at(a.src, 4u * (static_cast<uint32_t>(i * a.src_pitch) + xo)) : 0.f;
     }
+  };
+  double xh[2][4] = {};
+  double yh[2][4] = {};
+  read_down(-M);
+  for (int i0 = -M; i0 < L; i0 += kColAhead) {
+    float xin[kColAhead][2], fs[kColAhead];
+#pragma unroll
+    for (int j = 0; j < kColAhead; ++j) {
+      xin[j][0] = nx[j][0];
+      xin[j][1] = nx[j][1];
+      fs[j] = nf[j];
+    }
+    if (i0 + kColAhead < L) read_down(i0 + kColAhead);
 #pragma unroll
     for (int j = 0; j < kColAhead; ++j) {
       const int i = i0 + j;
       if (i >= L) break;
-      double S[4];
+      double S[2];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
+      for (int p = 0; p < 2; ++p) {
         xh[p][3] = xh[p][2];
         xh[p][2] = xh[p][1];
         xh[p][1] = xh[p][0];
@@ -391,36 +444,44 @@ __global__ void __launch_bounds__(kLineThreads) rec_cols_kernel(const RecArgs a)
       if (i >= 0) {
         double c, s;
         demod_phase(fs[j], &c, &s);
-        const size_t o = plane * k + (size_t)i * Wd + x0;
-        a.P[o] = dk * (c * S[0] + s * S[1]);
-        a.Q[o] = dk * (c * S[2] + s * S[3]);
+        st_at(share, 8u * (static_cast<uint32_t>(i * Wd) + xo), dk * (c * S[0] + s * S[1]));
       }
     }
   }
-  double xa[4][4] = {};
-  double ya[4][4] = {};
-  for (int i0 = L - 1 + M; i0 >= 0; i0 -= kColAhead) {
-    float xin[kColAhead][4], fs[kColAhead];
-    double po[kColAhead], qo[kColAhead];
+  // (the shares the upward sweep reads were written by this lane on the way down)
+  auto read_up = [&](int i0) {
 #pragma unroll
     for (int j = 0; j < kColAhead; ++j) {
       const int i = i0 - j;
-      const size_t r = (size_t)fold(i, L) * Wd;
-#pragma unroll
-      for (int p = 0; p < 4; ++p) xin[j][p] = i >= 0 ? in[p * plane + r] : 0.f;
+      const uint32_t r = 4u * (static_cast<uint32_t>(fold(i, L) * Wd) + xo);
+      nx[j][0] = i >= 0 ? ld_at(in0, r) : 0.f;
+      nx[j][1] = i >= 0 ? ld_at(in1, r) : 0.f;
       const bool out = i >= 0 && i < L;
-      const size_t o = plane * k + (size_t)(out ? i : 0) * Wd + x0;
-      fs[j] = out ? a.src[(size_t)i * a.src_pitch + x0] : 0.f;
-      po[j] = out ? a.P[o] : 0.0;
-      qo[j] = out ? a.Q[o] : 0.0;
+      nf[j] = out ? ld_at(a.src, 4u * (static_cast<uint32_t>(i * a.src_pitch) + xo)) : 0.f;
+      ns[j] = out ? ld_at(share, 8u * (static_cast<uint32_t>(i * Wd) + xo)) : 0.0;
     }
+  };
+  double xa[2][4] = {};
+  double ya[2][4] = {};
+  read_up(L - 1 + M);
+  for (int i0 = L - 1 + M; i0 >= 0; i0 -= kColAhead) {
+    float xin[kColAhead][2], fs[kColAhead];
+    double so[kColAhead];
+#pragma unroll
+    for (int j = 0; j < kColAhead; ++j) {
+      xin[j][0] = nx[j][0];
+      xin[j][1] = nx[j][1];
+      fs[j] = nf[j];
+      so[j] = ns[j];
+    }
+    if (i0 - kColAhead >= 0) read_up(i0 - kColAhead);
 #pragma unroll
     for (int j = 0; j < kColAhead; ++j) {
       const int i = i0 - j;
       if (i < 0) break;
-      double S[4];
+      double S[2];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
+      for (int p = 0; p < 2; ++p) {
         const double v = a.c.na[1] * xa[p][0] + a.c.na[2] * xa[p][1] + a.c.na[3] * xa[p][2] +
                          a.c.na[4] * xa[p][3] - a.c.dd[1] * ya[p][0] - a.c.dd[2] * ya[p][1] -
                          a.c.dd[3] * ya[p][2] - a.c.dd[4] * ya[p][3];
@@ -437,9 +498,7 @@ __global__ void __launch_bounds__(kLineThreads) rec_cols_kernel(const RecArgs a)
       if (i < L) {
         double c, s;
         demod_phase(fs[j], &c, &s);
-        const size_t o = plane * k + (size_t)i * Wd + x0;
-        a.P[o] = po[j] + dk * (c * S[0] + s * S[1]);
-        a.Q[o] = qo[j] + dk * (c * S[2] + s * S[3]);
+        st_at(share, 8u * (static_cast<uint32_t>(i * Wd) + xo), so[j] + dk * (c * S[0] + s * S[1]));
       }
     }
   }
@@ -480,6 +539,10 @@ int resolve_recursive(const bf_job* job, Resolved* r) {
   if (!(job->sigma_s > 0.0) || !std::isfinite(job->sigma_s))
     return fail(BF_E_INVALID, "sigma_s must be finite and > 0");
   if (job->sigma_s > kMaxSigmaRec) return fail(BF_E_UNSUPPORTED, "sigma_s exceeds 256");
+  // the kernels address f, the planes and the shares with 32-bit byte offsets
+  if (job->height >= 1 && job->width >= 1 &&
+      (size_t)job->height * (size_t)std::max(job->src_pitch, job->width) >= kMaxRecElems)
+    return fail(BF_E_UNSUPPORTED, "the recursive path takes images of fewer than 2^28 elements (rows x pitch)");
   // validation and fit shared with bf_filter; the window does not apply here
   bf_job j = *job;
   j.W = 0;
@@ -515,6 +578,7 @@ extern "C" int bf_filter_recursive(const bf_job* job, void* workspace, size_t ws
   a.T = job->T;
   a.integer = (job->flags & BF_FLAG_INTEGER_INPUT) ? 1 : 0;
   a.c0 = r.desc.c0;
+  a.F = r.desc.F;
   a.c = recursion_coefficients(job->sigma_s);
   a.K = K;
   const size_t planes = align256(4 * h * n * sizeof(float)), shares = align256(h * n * sizeof(double));
@@ -524,9 +588,9 @@ extern "C" int bf_filter_recursive(const bf_job* job, void* workspace, size_t ws
   for (int k = 0; k <= K; ++k) a.d[k] = r.desc.d[k];
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
   const dim3 grows((job->height + kLineThreads - 1) / kLineThreads, K + 1);
-  const dim3 gcols((job->width + kLineThreads - 1) / kLineThreads, K + 1);
+  const dim3 gcols((job->width + kLineThreads - 1) / kLineThreads, K + 1, 2);
   const size_t tab_bytes = a.integer ? 2 * (size_t)job->T * sizeof(float2) : 0;
-  hipLaunchKernelGGL(rec_rows_kernel, grows, dim3(kLineThreads), tab_bytes, stream, a);
+  hipLaunchKernelGGL(rec_rows_kernel, grows, dim3(kRowThreads), tab_bytes, stream, a);
   hipLaunchKernelGGL(rec_cols_kernel, gcols, dim3(kLineThreads), a.integer ? 2 * (size_t)job->T * sizeof(double2) : 0,
                      stream, a);
   hipLaunchKernelGGL(rec_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a);

@@ -297,6 +297,9 @@ def test_batched_rejects_outputs_that_overlap_other_jobs():
     (dict(sigma_r=-1.0), native.BF_E_INVALID),
     (dict(d=np.ones(300)), native.BF_E_UNSUPPORTED),
     (dict(dst=FAKE_SRC + 4 * 100), native.BF_E_INVALID),
+    # 2^28 elements: beyond the 32-bit byte offsets of the recursive kernels
+    (dict(height=16384, width=16384), native.BF_E_UNSUPPORTED),
+    (dict(height=8192, width=16384, src_pitch=32768), native.BF_E_UNSUPPORTED),
 ])
 def test_recursive_filter_rejects_bad_jobs_before_device_work(kw, code):
     j = _job(**kw)
@@ -309,8 +312,11 @@ def test_recursive_filter_rejects_bad_jobs_before_device_work(kw, code):
 
 
 def test_recursive_filter_workspace_checks():
-    # 24 (K + 1) bytes per pixel (row-smoothed planes, numerator and
-    # denominator shares), each of the three regions 256-byte aligned
+    # 32 (K + 1) bytes per pixel (row-smoothed float32 planes, float64
+    # numerator and denominator shares), each of the three regions 256-byte
+    # aligned; one row short of 2^28 elements is still taken
+    assert native.bf_recursive_workspace_bytes(_job(W=0, d=np.array([1.0]), height=16383, width=16384,
+                                                    dst=FAKE_SRC + (1 << 32))) > 0
     j = _job(W=0, d=np.array([1.0, 0.5, 0.25]))
     assert native.bf_recursive_workspace_bytes(j) == 32 * 3 * 64 * 64
     assert native.bf_recursive_workspace_bytes(_job(W=0, d=np.array([1.0]), height=3, width=5)) == 3 * 256
