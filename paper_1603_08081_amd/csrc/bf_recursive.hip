@@ -146,21 +146,26 @@ __device__ __forceinline__ void phase(float f, int k, int T, double* c, double* 
   sincospi(a / T, s, c);
 }
 
-// The row pass goes through LDS in blocks of 64 rows x kChunk positions: the
-// workgroup loads and stores whole row segments (coalesced) while each lane
-// walks its own row inside the block.  The four planes of a row are four
-// independent recursions: wavefront p of the workgroup runs plane p of the
-// block's 64 rows, so that four times as many wavefronts share the work of a
-// harmonic (one lane's recursion is a long dependent chain; more wavefronts
-// per SIMD hide more of its latency) and the block's f is staged once for
-// all four.
+// The row pass goes through LDS in blocks of 64 rows x kChunk positions,
+// double-buffered.  Four compute wavefronts run the four planes of the
+// block's rows (wavefront p: plane p, lane = row; the planes are independent
+// recursions), and two I/O wavefronts move the blocks between memory and LDS
+// (each for 32 of the rows; a transfer instruction covers 4 rows x kChunk
+// consecutive positions).  While the compute wavefronts run block b, the I/O
+// wavefronts store block b - 1's planes, stage block b + 1 from the registers
+// its reads landed in and start the reads of block b + 2, so that one barrier
+// per block is the only wait a compute wavefront has for memory (the I/O
+// wavefronts' waits for their reads and stores hold up nothing else).
 constexpr int kChunk = 16;
 constexpr int kTileStride = kChunk + 1;   // odd stride: a lane per row hits distinct banks
-constexpr int kRowThreads = 4 * kLineThreads;           // a wavefront per plane
-constexpr int kRowsPerPass = kRowThreads / kChunk;      // rows one block transfer instruction covers
-constexpr int kBlockRows = kLineThreads / kRowsPerPass;  // f transfers per thread and block
-static_assert(kRowThreads % kChunk == 0 && kLineThreads % kRowsPerPass == 0,
-              "block transfers split the workgroup into whole row segments");
+constexpr int kRowBlock = 64;             // rows of a workgroup (lanes of a compute wavefront)
+constexpr int kIoWaves = 2;
+constexpr int kRowThreads = (4 + kIoWaves) * kLineThreads;
+constexpr int kIoRowsPerInst = kLineThreads / kChunk;               // 4 rows per transfer instruction
+constexpr int kIoInsts = kRowBlock / kIoWaves / kIoRowsPerInst;      // 8 per I/O lane, plane and block
+constexpr int kTileFloats = kRowBlock * kTileStride;
+static_assert(kLineThreads % kChunk == 0 && kRowBlock % (kIoWaves * kIoRowsPerInst) == 0,
+              "I/O transfers cover whole row segments");
 
 // m = k f mod 2T for an integer image: f clamped to the gray levels 0..F the
 // integer flag promises (k f < 2^18 then, exact in float32); the quotient
@@ -191,162 +196,243 @@ __device__ __forceinline__ void st_at(double* base, uint32_t byte_off, double v)
   *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 
+// The row pass of one workgroup (64 rows, harmonic blockIdx.y).  INTEGER:
+// phases from the float32 table of cos/sin(pi m / T).
+template <bool INTEGER>
 __global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) {
-  __shared__ float ft[kLineThreads * kTileStride];       // f of the block
-  __shared__ float ot[4 * kLineThreads * kTileStride];   // the four planes of the block
-  extern __shared__ float2 cs_tab[];                     // 2T entries (cos, sin) when a.integer
+  __shared__ float ft[2][kTileFloats];       // f of the block
+  __shared__ float ot[2][4 * kTileFloats];   // the four planes of the block
+  extern __shared__ float2 cs_tab[];         // 2T entries (cos, sin) when INTEGER
   const int tid = threadIdx.x;
-  // the plane this wavefront runs (wave-uniform), and the lane's row
-  const int pl = __builtin_amdgcn_readfirstlane(tid / kLineThreads);
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kLineThreads);
   const int lane = tid % kLineThreads;
-  const int y0 = blockIdx.x * kLineThreads;
+  const int y0 = blockIdx.x * kRowBlock;
   const int k = blockIdx.y;
   const int L = a.width, M = a.c.margin;
-  const int nrows = min(kLineThreads, a.height - y0);
+  const int nrows = min(kRowBlock, a.height - y0);
   const size_t plane = (size_t)a.height * a.width;
   float* outk = a.rows + 4 * plane * k;
-  // in block transfers thread = (row offset r0, position q)
-  const int q = tid % kChunk, r0 = tid / kChunk;
-  const double c0 = a.c0;
-  if (a.integer) {
-    for (int m = tid; m < 2 * a.T; m += kRowThreads) {
+  const int T2 = 2 * a.T;
+  if (INTEGER) {
+    for (int m = tid; m < T2; m += kRowThreads) {
       double c, s;
       sincospi(static_cast<double>(m) / a.T, &s, &c);
       cs_tab[m] = make_float2(static_cast<float>(c), static_cast<float>(s));
     }
   }
-  __syncthreads();
-  const int T2 = 2 * a.T;
+  // blocks: causal pass b = 0 .. nb - 1 at positions -M + kChunk b ..;
+  // anti-causal pass from the top, block b at positions [lo, hi] with
+  // hi = L - 1 + M - kChunk b, lo = max(hi - kChunk + 1, 0)
+  const int nb = (L + M + kChunk - 1) / kChunk;
+  auto causal_i0 = [&](int b) { return -M + kChunk * b; };
+  auto anti_lo = [&](int b) { return max(L + M - kChunk * (b + 1), 0); };
+  auto anti_n = [&](int b) { return L - 1 + M - kChunk * b - anti_lo(b) + 1; };
+
+  if (wave >= 4) {
+    // ---- I/O wavefront: rows 32 h + r0 + 4 t, position q of the block
+    const int h = wave - 4;
+    const int q = lane % kChunk, r0 = h * (kRowBlock / kIoWaves) + lane / kChunk;
+    uint32_t srow[kIoInsts], orow[kIoInsts];  // byte offsets of the rows in f and in a plane
+#pragma unroll
+    for (int t = 0; t < kIoInsts; ++t) {
+      const int r = min(r0 + kIoRowsPerInst * t, nrows - 1);
+      srow[t] = 4u * static_cast<uint32_t>((y0 + r) * a.src_pitch);
+      orow[t] = 4u * static_cast<uint32_t>((y0 + r) * L);
+    }
+    auto row_ok = [&](int t) { return r0 + kIoRowsPerInst * t < nrows; };
+    float fv[kIoInsts], ov[4][kIoInsts];
+    // reads of causal block b (f at the block's position q)
+    auto read_causal = [&](int b) {
+      const int i = causal_i0(b) + q;
+      const bool ok = q < min(kChunk, L - causal_i0(b));
+      const uint32_t col = 4u * static_cast<uint32_t>(fold(i, L));
+#pragma unroll
+      for (int t = 0; t < kIoInsts; ++t) fv[t] = (ok && row_ok(t)) ? ld_at(a.src, srow[t] + col) : 0.f;
+    };
+    // reads of anti-causal block b: f and the four causal halves
+    auto read_anti = [&](int b) {
+      const int i = anti_lo(b) + q;
+      const bool ok = q < anti_n(b);
+      const uint32_t col = 4u * static_cast<uint32_t>(fold(i, L));
+      const uint32_t pos = 4u * static_cast<uint32_t>(min(i, L - 1));
+#pragma unroll
+      for (int t = 0; t < kIoInsts; ++t) {
+        fv[t] = (ok && row_ok(t)) ? ld_at(a.src, srow[t] + col) : 0.f;
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          ov[p][t] = (ok && row_ok(t) && i < L) ? ld_at(outk + p * plane, orow[t] + pos) : 0.f;
+      }
+    };
+    auto stage = [&](int buf, bool planes) {
+#pragma unroll
+      for (int t = 0; t < kIoInsts; ++t) {
+        const int r = r0 + kIoRowsPerInst * t;
+        ft[buf][r * kTileStride + q] = fv[t];
+        if (planes) {
+#pragma unroll
+          for (int p = 0; p < 4; ++p) ot[buf][p * kTileFloats + r * kTileStride + q] = ov[p][t];
+        }
+      }
+    };
+    // the planes of a block from LDS to memory, positions i0 + q (< L, >= 0),
+    // in two steps: fetch() reads them from LDS into registers, put() writes
+    // them out, so that the staging of the next block (which waits for its
+    // reads) can come between the two and not wait for these writes
+    float sv[4][kIoInsts];
+    auto fetch = [&](int buf) {
+#pragma unroll
+      for (int t = 0; t < kIoInsts; ++t) {
+        const int r = r0 + kIoRowsPerInst * t;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) sv[p][t] = ot[buf][p * kTileFloats + r * kTileStride + q];
+      }
+    };
+    auto put = [&](int i0, int n) {
+      const int i = i0 + q;
+      if (q >= n || i < 0 || i >= L) return;
+      const uint32_t pos = 4u * static_cast<uint32_t>(i);
+#pragma unroll
+      for (int t = 0; t < kIoInsts; ++t) {
+        if (!row_ok(t)) continue;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) st_at(outk + p * plane, orow[t] + pos, sv[p][t]);
+      }
+    };
+    read_causal(0);
+    stage(0, false);
+    if (nb > 1) read_causal(1);
+    __syncthreads();
+    for (int b = 0; b < nb; ++b) {
+      if (b >= 1) fetch((b - 1) & 1);
+      if (b + 1 < nb) {
+        stage((b + 1) & 1, false);
+        if (b + 2 < nb) read_causal(b + 2);
+      }
+      if (b >= 1) put(causal_i0(b - 1), min(kChunk, L - causal_i0(b - 1)));
+      __syncthreads();
+    }
+    fetch((nb - 1) & 1);
+    put(causal_i0(nb - 1), min(kChunk, L - causal_i0(nb - 1)));
+    // the causal halves of every block are in memory before any is read back
+    __syncthreads();
+    read_anti(0);
+    stage(0, true);
+    if (nb > 1) read_anti(1);
+    __syncthreads();
+    for (int b = 0; b < nb; ++b) {
+      // (block b + 1 is staged into the buffer block b - 1 leaves: fetched first)
+      if (b >= 1) fetch((b - 1) & 1);
+      if (b + 1 < nb) {
+        stage((b + 1) & 1, true);
+        if (b + 2 < nb) read_anti(b + 2);
+      }
+      if (b >= 1) put(anti_lo(b - 1), anti_n(b - 1));
+      __syncthreads();
+    }
+    fetch((nb - 1) & 1);
+    put(anti_lo(nb - 1), anti_n(nb - 1));
+    return;
+  }
+
+  // ---- compute wavefront: plane `wave` of row `lane`
+  const int pl = wave;
+  const double c0 = a.c0;
   const float inv_t2 = 1.0f / static_cast<float>(T2), fmax = static_cast<float>(a.F);
-  // this wavefront's plane of the modulated signal at gray level f
+  const double pbase = pl < 2 ? 1.0 : 0.0;  // the plane carries (f - c0) for p < 2
+  // plane pl of the modulated signal at gray level f:
+  // (f - c0) cos, (f - c0) sin, cos, sin of k w f for pl = 0, 1, 2, 3
   auto modulated = [&](float f) -> double {
     double c, s;
-    if (a.integer) {
+    if constexpr (INTEGER) {
       const float2 cs = cs_tab[phase_index(f, k, T2, inv_t2, fmax)];
       c = cs.x;
       s = cs.y;
     } else {
       phase(f, k, a.T, &c, &s);
     }
-    const double fc = (double)f - c0;
-    return pl == 0 ? fc * c : pl == 1 ? fc * s : pl == 2 ? c : s;
+    const double w = pbase != 0.0 ? (double)f - c0 : 1.0;
+    return w * ((pl & 1) ? s : c);
   };
-  float* const myot = ot + (size_t)pl * kLineThreads * kTileStride + lane * kTileStride;
-  // Each pass reads block b + 1 into registers while it runs block b, and
-  // needs two barriers per block: the one after staging (the block is in
-  // LDS) and the one after the recursions (the planes are in LDS); the copy
-  // of the planes out and the staging of the next block, both before the
-  // next first barrier, touch no LDS that a recursion of the other block uses.
-  //
-  // causal pass over positions -M .. L - 1
-  float fv[kBlockRows];  // f of the next block (column fold(i0 + q))
-  auto read_f = [&](int i0) {
-    const int col = fold(i0 + q, L);
-    const bool inb = q < min(kChunk, L - i0);
-#pragma unroll
-    for (int t = 0; t < kBlockRows; ++t) {
-      const int r = r0 + t * kRowsPerPass;
-      fv[t] = (inb && r < nrows) ? ld_at(a.src, 4u * (uint32_t)((y0 + r) * a.src_pitch + col)) : 0.f;
-    }
-  };
+  const bool active = lane < nrows;
+  // causal pass.  In a step the feedback terms come last, y(i-1)'s at the
+  // very end, so that one step waits on the previous step's result for a
+  // single multiply-add; for integer images the modulated values of a whole
+  // block are formed before its steps (their table reads do not wait on the
+  // recursion).
   double xh[4] = {};  // x(i), x(i-1), x(i-2), x(i-3)
   double yh[4] = {};  // y(i-1) .. y(i-4)
-  read_f(-M);
-  for (int i0 = -M; i0 < L; i0 += kChunk) {
-    const int n = min(kChunk, L - i0);
-    if (q < n) {
+  auto causal_step = [&](double x) -> float {
+    xh[3] = xh[2];
+    xh[2] = xh[1];
+    xh[1] = xh[0];
+    xh[0] = x;
+    const double ff = a.c.nc[0] * xh[0] + a.c.nc[1] * xh[1] + a.c.nc[2] * xh[2] + a.c.nc[3] * xh[3];
+    const double v = ff - a.c.dd[4] * yh[3] - a.c.dd[3] * yh[2] - a.c.dd[2] * yh[1] - a.c.dd[1] * yh[0];
+    yh[3] = yh[2];
+    yh[2] = yh[1];
+    yh[1] = yh[0];
+    yh[0] = v;
+    return static_cast<float>(v);
+  };
+  __syncthreads();
+  for (int b = 0; b < nb; ++b) {
+    const float* fr = ft[b & 1] + lane * kTileStride;
+    float* orow_l = ot[b & 1] + pl * kTileFloats + lane * kTileStride;
+    const int n = min(kChunk, L - causal_i0(b));
+    if (active) {
+      if (INTEGER && n == kChunk) {
+        double xv[kChunk];
 #pragma unroll
-      for (int t = 0; t < kBlockRows; ++t)
-        if (r0 + t * kRowsPerPass < nrows) ft[(r0 + t * kRowsPerPass) * kTileStride + q] = fv[t];
-    }
-    __syncthreads();
-    if (i0 + kChunk < L) read_f(i0 + kChunk);
-    if (lane < nrows) {
-      for (int j = 0; j < n; ++j) {
-        xh[3] = xh[2];
-        xh[2] = xh[1];
-        xh[1] = xh[0];
-        xh[0] = modulated(ft[lane * kTileStride + j]);
-        const double v = a.c.nc[0] * xh[0] + a.c.nc[1] * xh[1] + a.c.nc[2] * xh[2] + a.c.nc[3] * xh[3] -
-                         a.c.dd[1] * yh[0] - a.c.dd[2] * yh[1] - a.c.dd[3] * yh[2] - a.c.dd[4] * yh[3];
-        yh[3] = yh[2];
-        yh[2] = yh[1];
-        yh[1] = yh[0];
-        yh[0] = v;
-        myot[j] = static_cast<float>(v);
+        for (int j = 0; j < kChunk; ++j) xv[j] = modulated(fr[j]);
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) orow_l[j] = causal_step(xv[j]);
+      } else {
+        for (int j = 0; j < n; ++j) orow_l[j] = causal_step(modulated(fr[j]));
       }
     }
     __syncthreads();
-    if (q < n && i0 + q >= 0) {
-      for (int r = r0; r < nrows; r += kRowsPerPass)
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-          st_at(outk + p * plane, 4u * (uint32_t)((y0 + r) * L + i0 + q), ot[(p * kLineThreads + r) * kTileStride + q]);
-    }
   }
-  // anti-causal pass over positions L - 1 + M .. 0, blocks [lo, hi] from the top
-  float ov[4][kBlockRows];  // causal halves of the next block
-  auto read_block = [&](int hi) {
-    const int lo = max(hi - kChunk + 1, 0);
-    const int i = lo + q;
-    const int col = fold(i, L);
-    const bool inb = q <= hi - lo;
-#pragma unroll
-    for (int t = 0; t < kBlockRows; ++t) {
-      const int r = r0 + t * kRowsPerPass;
-      const bool ok = inb && r < nrows;
-      fv[t] = ok ? ld_at(a.src, 4u * (uint32_t)((y0 + r) * a.src_pitch + col)) : 0.f;
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-        ov[p][t] = (ok && i < L) ? ld_at(outk + p * plane, 4u * (uint32_t)((y0 + r) * L + i)) : 0.f;
-    }
-  };
-  __syncthreads();  // the last causal block's planes are out of LDS
+  __syncthreads();
+  // anti-causal pass: adds its half to the causal half in LDS
   double xa[4] = {};  // x(i+1) .. x(i+4)
   double ya[4] = {};  // y(i+1) .. y(i+4)
-  read_block(L - 1 + M);
-  for (int hi = L - 1 + M; hi >= 0; hi -= kChunk) {
-    const int lo = max(hi - kChunk + 1, 0);
-    const int n = hi - lo + 1;
-    if (q < n) {
-      const int i = lo + q;
+  auto anti_step = [&](double x) -> double {
+    const double ff = a.c.na[1] * xa[0] + a.c.na[2] * xa[1] + a.c.na[3] * xa[2] + a.c.na[4] * xa[3];
+    const double v = ff - a.c.dd[4] * ya[3] - a.c.dd[3] * ya[2] - a.c.dd[2] * ya[1] - a.c.dd[1] * ya[0];
+    ya[3] = ya[2];
+    ya[2] = ya[1];
+    ya[1] = ya[0];
+    ya[0] = v;
+    xa[3] = xa[2];
+    xa[2] = xa[1];
+    xa[1] = xa[0];
+    xa[0] = x;
+    return v;
+  };
+  __syncthreads();
+  for (int b = 0; b < nb; ++b) {
+    const float* fr = ft[b & 1] + lane * kTileStride;
+    float* orow_l = ot[b & 1] + pl * kTileFloats + lane * kTileStride;
+    const int lo = anti_lo(b), n = anti_n(b);
+    if (active) {
+      if (INTEGER && n == kChunk && lo + kChunk <= L) {
+        double xv[kChunk];
+        float cb[kChunk];
 #pragma unroll
-      for (int t = 0; t < kBlockRows; ++t) {
-        const int r = r0 + t * kRowsPerPass;
-        if (r < nrows) {
-          ft[r * kTileStride + q] = fv[t];
-          if (i < L) {
+        for (int j = 0; j < kChunk; ++j) {
+          xv[j] = modulated(fr[j]);
+          cb[j] = orow_l[j];
+        }
 #pragma unroll
-            for (int p = 0; p < 4; ++p) ot[(p * kLineThreads + r) * kTileStride + q] = ov[p][t];
-          }
+        for (int j = kChunk - 1; j >= 0; --j) orow_l[j] = static_cast<float>(cb[j] + anti_step(xv[j]));
+      } else {
+        for (int j = n - 1; j >= 0; --j) {
+          const double v = anti_step(modulated(fr[j]));
+          if (lo + j < L) orow_l[j] = static_cast<float>(orow_l[j] + v);
         }
       }
     }
     __syncthreads();
-    if (hi - kChunk >= 0) read_block(hi - kChunk);
-    if (lane < nrows) {
-      for (int j = n - 1; j >= 0; --j) {
-        const double x = modulated(ft[lane * kTileStride + j]);
-        const double v = a.c.na[1] * xa[0] + a.c.na[2] * xa[1] + a.c.na[3] * xa[2] + a.c.na[4] * xa[3] -
-                         a.c.dd[1] * ya[0] - a.c.dd[2] * ya[1] - a.c.dd[3] * ya[2] - a.c.dd[4] * ya[3];
-        ya[3] = ya[2];
-        ya[2] = ya[1];
-        ya[1] = ya[0];
-        ya[0] = v;
-        xa[3] = xa[2];
-        xa[2] = xa[1];
-        xa[1] = xa[0];
-        xa[0] = x;
-        if (lo + j < L) myot[j] = static_cast<float>(myot[j] + v);
-      }
-    }
-    __syncthreads();
-    if (q < n && lo + q < L) {
-      for (int r = r0; r < nrows; r += kRowsPerPass)
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-          st_at(outk + p * plane, 4u * (uint32_t)((y0 + r) * L + lo + q), ot[(p * kLineThreads + r) * kTileStride + q]);
-    }
   }
 }
 
@@ -432,9 +518,10 @@ __global__ void __launch_bounds__(kLineThreads) rec_cols_kernel(const RecArgs a)
         xh[p][2] = xh[p][1];
         xh[p][1] = xh[p][0];
         xh[p][0] = xin[j][p];
-        const double v = a.c.nc[0] * xh[p][0] + a.c.nc[1] * xh[p][1] + a.c.nc[2] * xh[p][2] +
-                         a.c.nc[3] * xh[p][3] - a.c.dd[1] * yh[p][0] - a.c.dd[2] * yh[p][1] -
-                         a.c.dd[3] * yh[p][2] - a.c.dd[4] * yh[p][3];
+        const double ff = a.c.nc[0] * xh[p][0] + a.c.nc[1] * xh[p][1] + a.c.nc[2] * xh[p][2] +
+                          a.c.nc[3] * xh[p][3];
+        const double v = ff - a.c.dd[4] * yh[p][3] - a.c.dd[3] * yh[p][2] - a.c.dd[2] * yh[p][1] -
+                         a.c.dd[1] * yh[p][0];
         yh[p][3] = yh[p][2];
         yh[p][2] = yh[p][1];
         yh[p][1] = yh[p][0];
@@ -482,9 +569,10 @@ __global__ void __launch_bounds__(kLineThreads) rec_cols_kernel(const RecArgs a)
       double S[2];
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
-        const double v = a.c.na[1] * xa[p][0] + a.c.na[2] * xa[p][1] + a.c.na[3] * xa[p][2] +
-                         a.c.na[4] * xa[p][3] - a.c.dd[1] * ya[p][0] - a.c.dd[2] * ya[p][1] -
-                         a.c.dd[3] * ya[p][2] - a.c.dd[4] * ya[p][3];
+        const double ff = a.c.na[1] * xa[p][0] + a.c.na[2] * xa[p][1] + a.c.na[3] * xa[p][2] +
+                          a.c.na[4] * xa[p][3];
+        const double v = ff - a.c.dd[4] * ya[p][3] - a.c.dd[3] * ya[p][2] - a.c.dd[2] * ya[p][1] -
+                         a.c.dd[1] * ya[p][0];
         ya[p][3] = ya[p][2];
         ya[p][2] = ya[p][1];
         ya[p][1] = ya[p][0];
@@ -587,10 +675,13 @@ extern "C" int bf_filter_recursive(const bf_job* job, void* workspace, size_t ws
   a.Q = reinterpret_cast<double*>(w + planes + shares);
   for (int k = 0; k <= K; ++k) a.d[k] = r.desc.d[k];
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-  const dim3 grows((job->height + kLineThreads - 1) / kLineThreads, K + 1);
+  const dim3 grows((job->height + kRowBlock - 1) / kRowBlock, K + 1);
   const dim3 gcols((job->width + kLineThreads - 1) / kLineThreads, K + 1, 2);
   const size_t tab_bytes = a.integer ? 2 * (size_t)job->T * sizeof(float2) : 0;
-  hipLaunchKernelGGL(rec_rows_kernel, grows, dim3(kRowThreads), tab_bytes, stream, a);
+  if (a.integer)
+    hipLaunchKernelGGL(rec_rows_kernel<true>, grows, dim3(kRowThreads), tab_bytes, stream, a);
+  else
+    hipLaunchKernelGGL(rec_rows_kernel<false>, grows, dim3(kRowThreads), 0, stream, a);
   hipLaunchKernelGGL(rec_cols_kernel, gcols, dim3(kLineThreads), a.integer ? 2 * (size_t)job->T * sizeof(double2) : 0,
                      stream, a);
   hipLaunchKernelGGL(rec_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a);
