@@ -203,13 +203,15 @@ def recursive_flops_per_px(K):
 
 def recursive_bytes_per_px(K):
     """Bytes per pixel the recursive-Gaussian path moves to and from memory
-    (before caches), per harmonic: the row pass reads f in both directions and
-    writes, re-reads and rewrites four float32 planes (56); the column pass
+    (before caches): per harmonic, the row pass reads f in both directions and
+    writes, re-reads and rewrites four float32 planes (56), the column pass
     reads them in both directions, and f in both directions for each of the
-    numerator and denominator shares, writes the two float64 shares on the
-    way down and reads and rewrites them on the way up (96); the final sum
-    reads the shares (16).  Plus the output."""
-    return (K + 1) * (56 + 96 + 16) + 4
+    numerator and denominator shares (48); per group of four harmonics, the
+    column pass writes the group's two float64 shares on the way down and
+    reads and rewrites them on the way up (48), and the final sum reads them
+    (16).  Plus the output."""
+    groups = (K + 4) // 4
+    return (K + 1) * (56 + 48) + groups * (48 + 16) + 4
 
 
 def run_recursive(args):

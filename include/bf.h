@@ -338,9 +338,10 @@ int bf_dynamic_range(const float* src, int height, int width, int src_pitch, int
  *               clamped into that range), otherwise phases are computed per
  *               pixel in float64
  *   workspace   device memory of at least bf_recursive_workspace_bytes(job)
- *               bytes (32 (K + 1) per pixel: the float32 row-smoothed planes
- *               of every harmonic and each harmonic's float64 shares of
- *               numerator and denominator), 256-byte aligned, owned by the
+ *               bytes (16 (K + 1) + 16 ceil((K + 1) / 4) per pixel: the
+ *               float32 row-smoothed planes of every harmonic and the float64
+ *               shares of numerator and denominator of every group of four
+ *               harmonics), 256-byte aligned, owned by the
  *               caller, not overlapping src or dst; in use until the stream
  *               has passed the launches
  *   hip_stream  stream to enqueue on: three launches, asynchronous

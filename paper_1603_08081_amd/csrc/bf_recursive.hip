@@ -13,9 +13,11 @@
 //               d_k: harmonic k's share of the numerator,
 //               cos S((f - c0) cos) + sin S((f - c0) sin), or of the
 //               denominator, cos S(cos) + sin S(sin), times d_k (the causal
-//               and anti-causal halves of S demodulated one after the other
-//               into the same share);
-//   3. one lane per pixel sums the K + 1 shares in float64, divides and adds c0.
+//               and anti-causal halves of S demodulated one after the
+//               other); the workgroup sums the shares of its four harmonics
+//               and writes one share per group;
+//   3. one lane per pixel sums the groups' shares in float64, divides and
+//      adds c0.
 // The recursions' state is float64; so are the phases: computed per pixel,
 // or for integer images looked up in a table of cos and sin of pi m / T
 // (m = k f mod 2T), float32 in the row pass and float64 in the column pass'
@@ -69,8 +71,9 @@ struct RecArgs {
   float c0;        // centre of the gray-level range
   RecCoef c;
   float* rows;     // [K + 1][4][height][width], row-smoothed planes
-  double* P;       // [K + 1][height][width], numerator shares
-  double* Q;       // [K + 1][height][width], denominator shares
+  int groups;      // groups of kColGroup harmonics, ceil((K + 1) / kColGroup)
+  double* P;       // [groups][height][width], numerator shares of the groups
+  double* Q;       // [groups][height][width], denominator shares of the groups
   double d[BF_MAX_K + 1];   // d_0..d_K
 };
 
@@ -437,68 +440,94 @@ __global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) 
 }
 
 // The column pass demodulates the causal and the anti-causal halves of each
-// smoothed plane separately (demodulation is linear): the causal sweep writes
-// harmonic k's shares of numerator and denominator from its half, and the
-// anti-causal sweep adds its own, so no causal half is stored.  The numerator
-// share needs planes 0 and 1 only, the denominator share planes 2 and 3:
-// blockIdx.z picks the pair, so that each lane runs two recursions and twice
-// as many wavefronts share the work.  Each sweep reads kColAhead positions at
-// a time, one batch ahead of the recursion steps.  For integer images the
-// demodulation's cos and sin of pi m / T, m = k f mod 2T, come from a float64
-// table in LDS built by the workgroup.
+// smoothed plane separately (demodulation is linear), and sums the
+// demodulated values of kColGroup harmonics inside the workgroup: the causal
+// sweep writes the group's share of numerator or denominator at each pixel,
+// and the anti-causal sweep adds the group's share of its own half, so that
+// neither a causal half nor a per-harmonic share goes to memory.  Workgroup =
+// kColGroup wavefronts, one harmonic each, lane = column; blockIdx.z picks
+// the numerator share (planes 0 and 1) or the denominator share (planes 2
+// and 3), so that each lane runs two recursions.  Each sweep reads
+// kColAhead positions at a time, one batch ahead of the recursion steps;
+// after a batch the wavefronts put their demodulated values in LDS and
+// wavefront w sums positions w, w + kColGroup, ... of the batch over the
+// group's harmonics in harmonic order.  For integer images the demodulation's cos and sin of
+// pi m / T, m = k f mod 2T, come from a float64 table in LDS built by the
+// workgroup.
 constexpr int kColAhead = 4;
-__global__ void __launch_bounds__(kLineThreads) rec_cols_kernel(const RecArgs a) {
+constexpr int kColGroup = 4;
+constexpr int kColSums = kColAhead / kColGroup;  // positions of a batch each wavefront sums
+static_assert(kColAhead % kColGroup == 0, "the wavefronts share a batch's sums evenly");
+constexpr int kColThreads = kColGroup * kLineThreads;
+
+__global__ void __launch_bounds__(kColThreads) rec_cols_kernel(const RecArgs a) {
   extern __shared__ double2 dcs_tab[];  // 2T entries (cos, sin) when a.integer
-  const int x0 = blockIdx.x * kLineThreads + threadIdx.x;
-  const int k = blockIdx.y;
+  __shared__ double red[2][kColGroup][kColAhead][kLineThreads];  // demodulated values of a batch
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kLineThreads);
+  const int lane = tid % kLineThreads;
+  const int x0 = blockIdx.x * kLineThreads + lane;
+  const int grp = blockIdx.y;
+  const int k = grp * kColGroup + wave;
+  const bool kon = k <= a.K;        // wave-uniform: the last group may be short
+  const bool xon = x0 < a.width;
+  const bool on = kon && xon;
   const int half = blockIdx.z;  // 0: numerator share (planes 0, 1); 1: denominator share (planes 2, 3)
   if (a.integer) {
-    for (int m = threadIdx.x; m < 2 * a.T; m += kLineThreads) {
+    for (int m = tid; m < 2 * a.T; m += kColThreads) {
       double c, s;
       sincospi(static_cast<double>(m) / a.T, &s, &c);
       dcs_tab[m] = make_double2(c, s);
     }
-    __syncthreads();
   }
-  if (x0 >= a.width) return;
+  __syncthreads();
   const int T2 = 2 * a.T;
   const float inv_t2 = 1.0f / static_cast<float>(T2), fmax = static_cast<float>(a.F);
   // cos and sin of k pi f / T for this column's pixels
+  const int kp = kon ? k : 0;  // (an idle wavefront's values are zero whatever its phases)
   auto demod_phase = [&](float f, double* c, double* s) {
     if (a.integer) {
-      const double2 cs = dcs_tab[phase_index(f, k, T2, inv_t2, fmax)];
+      const double2 cs = dcs_tab[phase_index(f, kp, T2, inv_t2, fmax)];
       *c = cs.x;
       *s = cs.y;
     } else {
-      phase(f, k, a.T, c, s);
+      phase(f, kp, a.T, c, s);
     }
   };
   const int L = a.height, M = a.c.margin, Wd = a.width;
   const size_t plane = (size_t)a.height * a.width;
   // wave-uniform bases; lane offsets in bytes
-  const float* in0 = a.rows + (4 * (size_t)k + 2 * half) * plane;
+  const float* in0 = a.rows + (4 * (size_t)kp + 2 * half) * plane;
   const float* in1 = in0 + plane;
-  double* share = (half ? a.Q : a.P) + plane * k;
-  const uint32_t xo = static_cast<uint32_t>(x0);
-  const double dk = a.d[k];
+  double* share = (half ? a.Q : a.P) + plane * grp;  // the group's share
+  const uint32_t xo = static_cast<uint32_t>(min(x0, Wd - 1));
+  const double dk = kon ? a.d[k] : 0.0;
+  // the sum over the group at position j of the batch in buffer buf
+  auto group_sum = [&](int buf, int j) -> double {
+    double acc = red[buf][0][j][lane];
+#pragma unroll
+    for (int h = 1; h < kColGroup; ++h) acc += red[buf][h][j][lane];
+    return acc;
+  };
   // the values of the next kColAhead positions are read while the current
   // ones run their recursion steps
   float nx[kColAhead][2], nf[kColAhead];
-  double ns[kColAhead];
+  double ns[kColSums] = {};  // the group's causal shares at this wavefront's positions of the next batch
   auto read_down = [&](int i0) {
 #pragma unroll
     for (int j = 0; j < kColAhead; ++j) {
       const int i = i0 + j;
       const uint32_t r = 4u * (static_cast<uint32_t>(fold(i, L) * Wd) + xo);
-      nx[j][0] = i < L ? ld_at(in0, r) : 0.f;
-      nx[j][1] = i < L ? ld_at(in1, r) : 0.f;
-      nf[j] = (i >= 0 && i < L) ? ld_at(a.src, 4u * (static_cast<uint32_t>(i * a.src_pitch) + xo)) : 0.f;
+      nx[j][0] = (on && i < L) ? ld_at(in0, r) : 0.f;
+      nx[j][1] = (on && i < L) ? ld_at(in1, r) : 0.f;
+      nf[j] = (on && i >= 0 && i < L) ? ld_at(a.src, 4u * (static_cast<uint32_t>(i * a.src_pitch) + xo)) : 0.f;
     }
   };
   double xh[2][4] = {};
   double yh[2][4] = {};
   read_down(-M);
-  for (int i0 = -M; i0 < L; i0 += kColAhead) {
+  int it = 0;
+  for (int i0 = -M; i0 < L; i0 += kColAhead, ++it) {
     float xin[kColAhead][2], fs[kColAhead];
 #pragma unroll
     for (int j = 0; j < kColAhead; ++j) {
@@ -507,99 +536,126 @@ __global__ void __launch_bounds__(kLineThreads) rec_cols_kernel(const RecArgs a)
       fs[j] = nf[j];
     }
     if (i0 + kColAhead < L) read_down(i0 + kColAhead);
+    const int buf = it & 1;
 #pragma unroll
     for (int j = 0; j < kColAhead; ++j) {
       const int i = i0 + j;
-      if (i >= L) break;
-      double S[2];
+      double sh = 0.0;
+      if (i < L) {
+        double S[2];
 #pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        xh[p][3] = xh[p][2];
-        xh[p][2] = xh[p][1];
-        xh[p][1] = xh[p][0];
-        xh[p][0] = xin[j][p];
-        const double ff = a.c.nc[0] * xh[p][0] + a.c.nc[1] * xh[p][1] + a.c.nc[2] * xh[p][2] +
-                          a.c.nc[3] * xh[p][3];
-        const double v = ff - a.c.dd[4] * yh[p][3] - a.c.dd[3] * yh[p][2] - a.c.dd[2] * yh[p][1] -
-                         a.c.dd[1] * yh[p][0];
-        yh[p][3] = yh[p][2];
-        yh[p][2] = yh[p][1];
-        yh[p][1] = yh[p][0];
-        yh[p][0] = v;
-        S[p] = v;
+        for (int p = 0; p < 2; ++p) {
+          xh[p][3] = xh[p][2];
+          xh[p][2] = xh[p][1];
+          xh[p][1] = xh[p][0];
+          xh[p][0] = xin[j][p];
+          const double ff = a.c.nc[0] * xh[p][0] + a.c.nc[1] * xh[p][1] + a.c.nc[2] * xh[p][2] +
+                            a.c.nc[3] * xh[p][3];
+          const double v = ff - a.c.dd[4] * yh[p][3] - a.c.dd[3] * yh[p][2] - a.c.dd[2] * yh[p][1] -
+                           a.c.dd[1] * yh[p][0];
+          yh[p][3] = yh[p][2];
+          yh[p][2] = yh[p][1];
+          yh[p][1] = yh[p][0];
+          yh[p][0] = v;
+          S[p] = v;
+        }
+        if (i >= 0) {
+          double c, s;
+          demod_phase(fs[j], &c, &s);
+          sh = dk * (c * S[0] + s * S[1]);
+        }
       }
-      if (i >= 0) {
-        double c, s;
-        demod_phase(fs[j], &c, &s);
-        st_at(share, 8u * (static_cast<uint32_t>(i * Wd) + xo), dk * (c * S[0] + s * S[1]));
-      }
+      red[buf][wave][j][lane] = sh;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kColSums; ++u) {
+      const int j = wave + kColGroup * u, i = i0 + j;
+      if (xon && i >= 0 && i < L) st_at(share, 8u * (static_cast<uint32_t>(i * Wd) + xo), group_sum(buf, j));
     }
   }
-  // (the shares the upward sweep reads were written by this lane on the way down)
+  // (the group shares the upward sweep reads were written on the way down by
+  // wavefronts of this workgroup, before at least one barrier)
   auto read_up = [&](int i0) {
 #pragma unroll
     for (int j = 0; j < kColAhead; ++j) {
       const int i = i0 - j;
       const uint32_t r = 4u * (static_cast<uint32_t>(fold(i, L) * Wd) + xo);
-      nx[j][0] = i >= 0 ? ld_at(in0, r) : 0.f;
-      nx[j][1] = i >= 0 ? ld_at(in1, r) : 0.f;
+      nx[j][0] = (on && i >= 0) ? ld_at(in0, r) : 0.f;
+      nx[j][1] = (on && i >= 0) ? ld_at(in1, r) : 0.f;
       const bool out = i >= 0 && i < L;
-      nf[j] = out ? ld_at(a.src, 4u * (static_cast<uint32_t>(i * a.src_pitch) + xo)) : 0.f;
-      ns[j] = out ? ld_at(share, 8u * (static_cast<uint32_t>(i * Wd) + xo)) : 0.0;
+      nf[j] = (on && out) ? ld_at(a.src, 4u * (static_cast<uint32_t>(i * a.src_pitch) + xo)) : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < kColSums; ++u) {
+      const int i = i0 - wave - kColGroup * u;
+      ns[u] = (xon && i >= 0 && i < L) ? ld_at(share, 8u * (static_cast<uint32_t>(i * Wd) + xo)) : 0.0;
     }
   };
   double xa[2][4] = {};
   double ya[2][4] = {};
   read_up(L - 1 + M);
-  for (int i0 = L - 1 + M; i0 >= 0; i0 -= kColAhead) {
+  for (int i0 = L - 1 + M; i0 >= 0; i0 -= kColAhead, ++it) {
     float xin[kColAhead][2], fs[kColAhead];
-    double so[kColAhead];
 #pragma unroll
     for (int j = 0; j < kColAhead; ++j) {
       xin[j][0] = nx[j][0];
       xin[j][1] = nx[j][1];
       fs[j] = nf[j];
-      so[j] = ns[j];
     }
+    double so[kColSums];
+#pragma unroll
+    for (int u = 0; u < kColSums; ++u) so[u] = ns[u];
     if (i0 - kColAhead >= 0) read_up(i0 - kColAhead);
+    const int buf = it & 1;
 #pragma unroll
     for (int j = 0; j < kColAhead; ++j) {
       const int i = i0 - j;
-      if (i < 0) break;
-      double S[2];
+      double sh = 0.0;
+      if (i >= 0) {
+        double S[2];
 #pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        const double ff = a.c.na[1] * xa[p][0] + a.c.na[2] * xa[p][1] + a.c.na[3] * xa[p][2] +
-                          a.c.na[4] * xa[p][3];
-        const double v = ff - a.c.dd[4] * ya[p][3] - a.c.dd[3] * ya[p][2] - a.c.dd[2] * ya[p][1] -
-                         a.c.dd[1] * ya[p][0];
-        ya[p][3] = ya[p][2];
-        ya[p][2] = ya[p][1];
-        ya[p][1] = ya[p][0];
-        ya[p][0] = v;
-        xa[p][3] = xa[p][2];
-        xa[p][2] = xa[p][1];
-        xa[p][1] = xa[p][0];
-        xa[p][0] = xin[j][p];
-        S[p] = v;
+        for (int p = 0; p < 2; ++p) {
+          const double ff = a.c.na[1] * xa[p][0] + a.c.na[2] * xa[p][1] + a.c.na[3] * xa[p][2] +
+                            a.c.na[4] * xa[p][3];
+          const double v = ff - a.c.dd[4] * ya[p][3] - a.c.dd[3] * ya[p][2] - a.c.dd[2] * ya[p][1] -
+                           a.c.dd[1] * ya[p][0];
+          ya[p][3] = ya[p][2];
+          ya[p][2] = ya[p][1];
+          ya[p][1] = ya[p][0];
+          ya[p][0] = v;
+          xa[p][3] = xa[p][2];
+          xa[p][2] = xa[p][1];
+          xa[p][1] = xa[p][0];
+          xa[p][0] = xin[j][p];
+          S[p] = v;
+        }
+        if (i < L) {
+          double c, s;
+          demod_phase(fs[j], &c, &s);
+          sh = dk * (c * S[0] + s * S[1]);
+        }
       }
-      if (i < L) {
-        double c, s;
-        demod_phase(fs[j], &c, &s);
-        st_at(share, 8u * (static_cast<uint32_t>(i * Wd) + xo), so[j] + dk * (c * S[0] + s * S[1]));
-      }
+      red[buf][wave][j][lane] = sh;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kColSums; ++u) {
+      const int j = wave + kColGroup * u, i = i0 - j;
+      if (xon && i >= 0 && i < L) st_at(share, 8u * (static_cast<uint32_t>(i * Wd) + xo), so[u] + group_sum(buf, j));
     }
   }
 }
 
+// one lane per pixel: the group shares summed in group order, the division, + c0
 __global__ void __launch_bounds__(256) rec_sum_kernel(const RecArgs a) {
   const size_t n = (size_t)a.height * a.width;
   const size_t o = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (o >= n) return;
   double p = 0.0, q = 0.0;
-  for (int k = 0; k <= a.K; ++k) {
-    p += a.P[n * k + o];
-    q += a.Q[n * k + o];
+  for (int g = 0; g < a.groups; ++g) {
+    p += a.P[n * g + o];
+    q += a.Q[n * g + o];
   }
   const int y = static_cast<int>(o / a.width), x = static_cast<int>(o % a.width);
   a.dst[(size_t)y * a.dst_pitch + x] = static_cast<float>(p / q + (double)a.c0);
@@ -607,10 +663,13 @@ __global__ void __launch_bounds__(256) rec_sum_kernel(const RecArgs a) {
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-// layout: row-smoothed planes (float32), numerator shares, denominator shares (float64)
+int rec_groups(int K) { return (K + kColGroup) / kColGroup; }
+
+// layout: row-smoothed planes of every harmonic (float32), numerator shares
+// and denominator shares of every group of kColGroup harmonics (float64)
 size_t rec_ws_bytes(int height, int width, int K) {
-  const size_t n = (size_t)height * width, h = (size_t)K + 1;
-  return align256(4 * h * n * sizeof(float)) + 2 * align256(h * n * sizeof(double));
+  const size_t n = (size_t)height * width, h = (size_t)K + 1, g = (size_t)rec_groups(K);
+  return align256(4 * h * n * sizeof(float)) + 2 * align256(g * n * sizeof(double));
 }
 
 }  // namespace
@@ -669,20 +728,22 @@ extern "C" int bf_filter_recursive(const bf_job* job, void* workspace, size_t ws
   a.F = r.desc.F;
   a.c = recursion_coefficients(job->sigma_s);
   a.K = K;
-  const size_t planes = align256(4 * h * n * sizeof(float)), shares = align256(h * n * sizeof(double));
+  a.groups = rec_groups(K);
+  const size_t planes = align256(4 * h * n * sizeof(float)),
+               shares = align256((size_t)a.groups * n * sizeof(double));
   a.rows = reinterpret_cast<float*>(w);
   a.P = reinterpret_cast<double*>(w + planes);
   a.Q = reinterpret_cast<double*>(w + planes + shares);
   for (int k = 0; k <= K; ++k) a.d[k] = r.desc.d[k];
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
   const dim3 grows((job->height + kRowBlock - 1) / kRowBlock, K + 1);
-  const dim3 gcols((job->width + kLineThreads - 1) / kLineThreads, K + 1, 2);
+  const dim3 gcols((job->width + kLineThreads - 1) / kLineThreads, a.groups, 2);
   const size_t tab_bytes = a.integer ? 2 * (size_t)job->T * sizeof(float2) : 0;
   if (a.integer)
     hipLaunchKernelGGL(rec_rows_kernel<true>, grows, dim3(kRowThreads), tab_bytes, stream, a);
   else
     hipLaunchKernelGGL(rec_rows_kernel<false>, grows, dim3(kRowThreads), 0, stream, a);
-  hipLaunchKernelGGL(rec_cols_kernel, gcols, dim3(kLineThreads), a.integer ? 2 * (size_t)job->T * sizeof(double2) : 0,
+  hipLaunchKernelGGL(rec_cols_kernel, gcols, dim3(kColThreads), a.integer ? 2 * (size_t)job->T * sizeof(double2) : 0,
                      stream, a);
   hipLaunchKernelGGL(rec_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a);
   const hipError_t e = hipGetLastError();

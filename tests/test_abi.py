@@ -312,13 +312,15 @@ def test_recursive_filter_rejects_bad_jobs_before_device_work(kw, code):
 
 
 def test_recursive_filter_workspace_checks():
-    # 32 (K + 1) bytes per pixel (row-smoothed float32 planes, float64
-    # numerator and denominator shares), each of the three regions 256-byte
-    # aligned; one row short of 2^28 elements is still taken
+    # 16 (K + 1) + 16 ceil((K + 1) / 4) bytes per pixel (row-smoothed
+    # float32 planes, float64 numerator and denominator shares of each group
+    # of four harmonics), each of the three regions 256-byte aligned; one row
+    # short of 2^28 elements is still taken
     assert native.bf_recursive_workspace_bytes(_job(W=0, d=np.array([1.0]), height=16383, width=16384,
                                                     dst=FAKE_SRC + (1 << 32))) > 0
     j = _job(W=0, d=np.array([1.0, 0.5, 0.25]))
-    assert native.bf_recursive_workspace_bytes(j) == 32 * 3 * 64 * 64
+    assert native.bf_recursive_workspace_bytes(j) == (16 * 3 + 16 * 1) * 64 * 64
+    assert native.bf_recursive_workspace_bytes(_job(W=0, d=np.ones(6))) == (16 * 6 + 16 * 2) * 64 * 64
     assert native.bf_recursive_workspace_bytes(_job(W=0, d=np.array([1.0]), height=3, width=5)) == 3 * 256
     ws = native.bf_recursive_workspace_bytes(j)
     for ptr, n in ((None, ws), (0x30000000, ws - 1), (0x30000004, ws)):
