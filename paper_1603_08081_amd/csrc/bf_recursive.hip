@@ -152,8 +152,8 @@ __device__ __forceinline__ void phase(float f, int k, int T, double* c, double* 
 // The row pass goes through LDS in blocks of 64 rows x kChunk positions,
 // double-buffered.  Four compute wavefronts run the four planes of the
 // block's rows (wavefront p: plane p, lane = row; the planes are independent
-// recursions), and two I/O wavefronts move the blocks between memory and LDS
-// (each for 32 of the rows; a transfer instruction covers 4 rows x kChunk
+// recursions), and four I/O wavefronts move the blocks between memory and LDS
+// (each for 16 of the rows; a transfer instruction covers 4 rows x kChunk
 // consecutive positions).  While the compute wavefronts run block b, the I/O
 // wavefronts store block b - 1's planes, stage block b + 1 from the registers
 // its reads landed in and start the reads of block b + 2, so that one barrier
@@ -162,10 +162,10 @@ __device__ __forceinline__ void phase(float f, int k, int T, double* c, double* 
 constexpr int kChunk = 16;
 constexpr int kTileStride = kChunk + 1;   // odd stride: a lane per row hits distinct banks
 constexpr int kRowBlock = 64;             // rows of a workgroup (lanes of a compute wavefront)
-constexpr int kIoWaves = 2;
+constexpr int kIoWaves = 4;
 constexpr int kRowThreads = (4 + kIoWaves) * kLineThreads;
 constexpr int kIoRowsPerInst = kLineThreads / kChunk;               // 4 rows per transfer instruction
-constexpr int kIoInsts = kRowBlock / kIoWaves / kIoRowsPerInst;      // 8 per I/O lane, plane and block
+constexpr int kIoInsts = kRowBlock / kIoWaves / kIoRowsPerInst;      // 4 per I/O lane, plane and block
 constexpr int kTileFloats = kRowBlock * kTileStride;
 static_assert(kLineThreads % kChunk == 0 && kRowBlock % (kIoWaves * kIoRowsPerInst) == 0,
               "I/O transfers cover whole row segments");
@@ -235,13 +235,14 @@ __global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) 
     // ---- I/O wavefront: rows 32 h + r0 + 4 t, position q of the block
     const int h = wave - 4;
     const int q = lane % kChunk, r0 = h * (kRowBlock / kIoWaves) + lane / kChunk;
-    uint32_t srow[kIoInsts], orow[kIoInsts];  // byte offsets of the rows in f and in a plane
-#pragma unroll
-    for (int t = 0; t < kIoInsts; ++t) {
-      const int r = min(r0 + kIoRowsPerInst * t, nrows - 1);
-      srow[t] = 4u * static_cast<uint32_t>((y0 + r) * a.src_pitch);
-      orow[t] = 4u * static_cast<uint32_t>((y0 + r) * L);
-    }
+    // byte offsets of row r0 + 4 t in f and in a plane (rows past the image
+    // are never accessed: row_ok masks them)
+    const uint32_t s_row0 = 4u * static_cast<uint32_t>((y0 + r0) * a.src_pitch),
+                   s_step = 4u * static_cast<uint32_t>(kIoRowsPerInst * a.src_pitch);
+    const uint32_t o_row0 = 4u * static_cast<uint32_t>((y0 + r0) * L),
+                   o_step = 4u * static_cast<uint32_t>(kIoRowsPerInst * L);
+    auto srow = [&](int t) { return s_row0 + static_cast<uint32_t>(t) * s_step; };
+    auto orow = [&](int t) { return o_row0 + static_cast<uint32_t>(t) * o_step; };
     auto row_ok = [&](int t) { return r0 + kIoRowsPerInst * t < nrows; };
     float fv[kIoInsts], ov[4][kIoInsts];
     // reads of causal block b (f at the block's position q)
@@ -250,7 +251,7 @@ __global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) 
       const bool ok = q < min(kChunk, L - causal_i0(b));
       const uint32_t col = 4u * static_cast<uint32_t>(fold(i, L));
 #pragma unroll
-      for (int t = 0; t < kIoInsts; ++t) fv[t] = (ok && row_ok(t)) ? ld_at(a.src, srow[t] + col) : 0.f;
+      for (int t = 0; t < kIoInsts; ++t) fv[t] = (ok && row_ok(t)) ? ld_at(a.src, srow(t) + col) : 0.f;
     };
     // reads of anti-causal block b: f and the four causal halves
     auto read_anti = [&](int b) {
@@ -260,10 +261,10 @@ __global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) 
       const uint32_t pos = 4u * static_cast<uint32_t>(min(i, L - 1));
 #pragma unroll
       for (int t = 0; t < kIoInsts; ++t) {
-        fv[t] = (ok && row_ok(t)) ? ld_at(a.src, srow[t] + col) : 0.f;
+        fv[t] = (ok && row_ok(t)) ? ld_at(a.src, srow(t) + col) : 0.f;
 #pragma unroll
         for (int p = 0; p < 4; ++p)
-          ov[p][t] = (ok && row_ok(t) && i < L) ? ld_at(outk + p * plane, orow[t] + pos) : 0.f;
+          ov[p][t] = (ok && row_ok(t) && i < L) ? ld_at(outk + p * plane, orow(t) + pos) : 0.f;
       }
     };
     auto stage = [&](int buf, bool planes) {
@@ -298,7 +299,7 @@ __global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) 
       for (int t = 0; t < kIoInsts; ++t) {
         if (!row_ok(t)) continue;
 #pragma unroll
-        for (int p = 0; p < 4; ++p) st_at(outk + p * plane, orow[t] + pos, sv[p][t]);
+        for (int p = 0; p < 4; ++p) st_at(outk + p * plane, orow(t) + pos, sv[p][t]);
       }
     };
     read_causal(0);
@@ -359,9 +360,7 @@ __global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) 
   const bool active = lane < nrows;
   // causal pass.  In a step the feedback terms come last, y(i-1)'s at the
   // very end, so that one step waits on the previous step's result for a
-  // single multiply-add; for integer images the modulated values of a whole
-  // block are formed before its steps (their table reads do not wait on the
-  // recursion).
+  // single multiply-add.
   double xh[4] = {};  // x(i), x(i-1), x(i-2), x(i-3)
   double yh[4] = {};  // y(i-1) .. y(i-4)
   auto causal_step = [&](double x) -> float {
@@ -383,12 +382,9 @@ __global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) 
     float* orow_l = ot[b & 1] + pl * kTileFloats + lane * kTileStride;
     const int n = min(kChunk, L - causal_i0(b));
     if (active) {
-      if (INTEGER && n == kChunk) {
-        double xv[kChunk];
+      if (n == kChunk) {
 #pragma unroll
-        for (int j = 0; j < kChunk; ++j) xv[j] = modulated(fr[j]);
-#pragma unroll
-        for (int j = 0; j < kChunk; ++j) orow_l[j] = causal_step(xv[j]);
+        for (int j = 0; j < kChunk; ++j) orow_l[j] = causal_step(modulated(fr[j]));
       } else {
         for (int j = 0; j < n; ++j) orow_l[j] = causal_step(modulated(fr[j]));
       }
@@ -418,16 +414,10 @@ __global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) 
     float* orow_l = ot[b & 1] + pl * kTileFloats + lane * kTileStride;
     const int lo = anti_lo(b), n = anti_n(b);
     if (active) {
-      if (INTEGER && n == kChunk && lo + kChunk <= L) {
-        double xv[kChunk];
-        float cb[kChunk];
+      if (n == kChunk && lo + kChunk <= L) {
 #pragma unroll
-        for (int j = 0; j < kChunk; ++j) {
-          xv[j] = modulated(fr[j]);
-          cb[j] = orow_l[j];
-        }
-#pragma unroll
-        for (int j = kChunk - 1; j >= 0; --j) orow_l[j] = static_cast<float>(cb[j] + anti_step(xv[j]));
+        for (int j = kChunk - 1; j >= 0; --j)
+          orow_l[j] = static_cast<float>(orow_l[j] + anti_step(modulated(fr[j])));
       } else {
         for (int j = n - 1; j >= 0; --j) {
           const double v = anti_step(modulated(fr[j]));
@@ -454,7 +444,7 @@ __global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) 
 // group's harmonics in harmonic order.  For integer images the demodulation's cos and sin of
 // pi m / T, m = k f mod 2T, come from a float64 table in LDS built by the
 // workgroup.
-constexpr int kColAhead = 4;
+constexpr int kColAhead = 8;
 constexpr int kColGroup = 4;
 constexpr int kColSums = kColAhead / kColGroup;  // positions of a batch each wavefront sums
 static_assert(kColAhead % kColGroup == 0, "the wavefronts share a batch's sums evenly");
