@@ -153,19 +153,19 @@ __device__ __forceinline__ void phase(float f, int k, int T, double* c, double* 
 // double-buffered.  Four compute wavefronts run the four planes of the
 // block's rows (wavefront p: plane p, lane = row; the planes are independent
 // recursions), and four I/O wavefronts move the blocks between memory and LDS
-// (each for 16 of the rows; a transfer instruction covers 4 rows x kChunk
-// consecutive positions).  While the compute wavefronts run block b, the I/O
+// (each for 16 of the rows; a transfer instruction covers 2 rows x kChunk
+// consecutive positions, whole 128-byte lines).  While the compute wavefronts run block b, the I/O
 // wavefronts store block b - 1's planes, stage block b + 1 from the registers
 // its reads landed in and start the reads of block b + 2, so that one barrier
 // per block is the only wait a compute wavefront has for memory (the I/O
 // wavefronts' waits for their reads and stores hold up nothing else).
-constexpr int kChunk = 16;
+constexpr int kChunk = 32;
 constexpr int kTileStride = kChunk + 1;   // odd stride: a lane per row hits distinct banks
 constexpr int kRowBlock = 64;             // rows of a workgroup (lanes of a compute wavefront)
 constexpr int kIoWaves = 4;
 constexpr int kRowThreads = (4 + kIoWaves) * kLineThreads;
-constexpr int kIoRowsPerInst = kLineThreads / kChunk;               // 4 rows per transfer instruction
-constexpr int kIoInsts = kRowBlock / kIoWaves / kIoRowsPerInst;      // 4 per I/O lane, plane and block
+constexpr int kIoRowsPerInst = kLineThreads / kChunk;               // 2 rows per transfer instruction
+constexpr int kIoInsts = kRowBlock / kIoWaves / kIoRowsPerInst;      // 8 per I/O lane, plane and block
 constexpr int kTileFloats = kRowBlock * kTileStride;
 static_assert(kLineThreads % kChunk == 0 && kRowBlock % (kIoWaves * kIoRowsPerInst) == 0,
               "I/O transfers cover whole row segments");
