@@ -25,10 +25,12 @@
 // are float32, the shares float64 (the denominator of a wide spatial kernel
 // can be a small difference of much larger shares, which float32 shares would
 // leave with errors above 1e-3 gray levels).  Centring f on c0 halves the
-// magnitude of the weighted planes and so their rounding.  Every lane reads
-// the values of several positions before it uses any of them, so that the
-// memory latency of a recursion step overlaps the arithmetic of the others.  The recursion coefficients come from the four poles of
-// Deriche's two damped cosine/sine pairs (his published fit of exp(-x^2/2)):
+// magnitude of the weighted planes and so their rounding.  Reads run ahead
+// of the recursion steps that use them (the row pass's I/O wavefronts one
+// block ahead, the column lanes one batch of positions ahead), so that memory
+// latency overlaps arithmetic.  The recursion coefficients come from the four
+// poles of Deriche's two damped cosine/sine pairs (his published fit of
+// exp(-x^2/2)):
 // the causal half of the kernel is a sum of four one-pole terms, whose common
 // denominator and numerator give the recursion, and the anti-causal half
 // (n >= 1, run backwards) has numerator N(z) - g(0) D(z).  Scaled to unit sum.
@@ -154,11 +156,12 @@ __device__ __forceinline__ void phase(float f, int k, int T, double* c, double* 
 // block's rows (wavefront p: plane p, lane = row; the planes are independent
 // recursions), and four I/O wavefronts move the blocks between memory and LDS
 // (each for 16 of the rows; a transfer instruction covers 2 rows x kChunk
-// consecutive positions, whole 128-byte lines).  While the compute wavefronts run block b, the I/O
-// wavefronts store block b - 1's planes, stage block b + 1 from the registers
-// its reads landed in and start the reads of block b + 2, so that one barrier
-// per block is the only wait a compute wavefront has for memory (the I/O
-// wavefronts' waits for their reads and stores hold up nothing else).
+// consecutive positions, whole 128-byte lines).  While the compute
+// wavefronts run block b, the I/O wavefronts store block b - 1's planes,
+// stage block b + 1 from the registers its reads landed in and start the
+// reads of block b + 2, so that one barrier per block is the only wait a
+// compute wavefront has for memory (the I/O wavefronts' waits for their
+// reads and stores hold up nothing else).
 constexpr int kChunk = 32;
 constexpr int kTileStride = kChunk + 1;   // odd stride: a lane per row hits distinct banks
 constexpr int kRowBlock = 64;             // rows of a workgroup (lanes of a compute wavefront)
