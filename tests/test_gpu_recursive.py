@@ -40,6 +40,22 @@ def test_matches_the_oracle_on_integer_images(H, Wd, sigma_s, sigma_r, seed):
     assert np.abs(out - want).max() <= TOL
 
 
+@pytest.mark.parametrize("T,f_max,sigma_r", [
+    (1000, 0, 30.0),    # 10-bit gray levels: a 2000-entry phase table, K = 41 (11 groups, last one short)
+    (31, 0, 3.0),       # 5-bit gray levels
+    (255, 200, 20.0),   # gray levels 0..200 < T: centring on f_max / 2, indices clamped to 0..200
+])
+def test_other_gray_level_ranges(T, f_max, sigma_r):
+    top = f_max if f_max else T
+    f = np.round(polygon_image(48, 90, 21) * (top / 255.0)).astype(np.float32)
+    fit = oracle.fit_kernel("gaussian", sigma_r, T, 1e-3)
+    print("recursive T", T, "f_max", f_max, "K", fit.K, flush=True)
+    out, st = _run(f, sigma_s=4.0, T=T, d=fit.d, integer_input=True, f_max=f_max)
+    want = R.fourier_recursive(f, 4.0, fit.d, T)
+    assert st == 0
+    assert np.abs(out - want).max() <= TOL
+
+
 def test_fit_on_the_device_side_and_non_integer_image():
     rng = np.random.default_rng(7)
     f = (polygon_image(40, 72, 5) + rng.uniform(-0.5, 0.5, (40, 72))).clip(0, 255).astype(np.float32)
