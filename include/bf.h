@@ -365,7 +365,7 @@ const char* bf_last_error(void);
  *   BF_BATCH_GRID=items|<n>    workgroups per class launch: one per tile, or
  *                  a fixed n; unset = a persistent grid sized by occupancy;
  *                  read at plan creation.
- * While either of the first two is set, remembered tuner choices are not
+ * While either is set, remembered tuner choices are not
  * applied at plan creation; bf_plan_tune still times and sets the geometry.
  */
 
