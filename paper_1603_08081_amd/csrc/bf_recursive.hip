@@ -127,8 +127,10 @@ RecCoef recursion_coefficients(double sigma) {
   const double total = (sum_n + sum_a) / sum_d;
   for (int q = 0; q < 4; ++q) c.nc[q] /= total;
   for (int q = 1; q < 5; ++q) c.na[q] /= total;
-  // the slowest decay is e^{-b n / sigma}: beyond this the kernel is < 1e-16 of its peak
-  c.margin = static_cast<int>(std::ceil(sigma * 16.0 * std::log(10.0) / kFitDecay[1])) + 8;
+  // the slowest decay is e^{-b n / sigma}: beyond this the kernel is < 1e-16 of
+  // its peak; rounded up to whole 32-position blocks so that the row pass's
+  // blocks inside the image start on 16-byte boundaries
+  c.margin = (static_cast<int>(std::ceil(sigma * 16.0 * std::log(10.0) / kFitDecay[1])) + 8 + 31) / 32 * 32;
   return c;
 }
 
@@ -155,8 +157,9 @@ __device__ __forceinline__ void phase(float f, int k, int T, double* c, double* 
 // double-buffered.  Four compute wavefronts run the four planes of the
 // block's rows (wavefront p: plane p, lane = row; the planes are independent
 // recursions), and four I/O wavefronts move the blocks between memory and LDS
-// (each for 16 of the rows; a transfer instruction covers 2 rows x kChunk
-// consecutive positions, whole 128-byte lines).  While the compute
+// (each for 16 of the rows; a transfer instruction covers 8 rows x kChunk
+// consecutive positions as 16-byte reads and writes where the block lies
+// inside the row, 2 rows x kChunk single floats elsewhere).  While the compute
 // wavefronts run block b, the I/O wavefronts store block b - 1's planes,
 // stage block b + 1 from the registers its reads landed in and start the
 // reads of block b + 2, so that one barrier per block is the only wait a
@@ -247,9 +250,39 @@ __global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) 
     auto srow = [&](int t) { return s_row0 + static_cast<uint32_t>(t) * s_step; };
     auto orow = [&](int t) { return o_row0 + static_cast<uint32_t>(t) * o_step; };
     auto row_ok = [&](int t) { return r0 + kIoRowsPerInst * t < nrows; };
+    // float4 form of a block that lies inside the row and starts on a
+    // 16-byte boundary: lane = (row rv, quad c4 of 4 positions); this wave
+    // keeps its 16 rows, so a block in either form and the next one in the
+    // other touch the same LDS elements from the same wave
+    const bool vec_ok = (L % 4) == 0 && (a.src_pitch % 4) == 0 &&
+                        (reinterpret_cast<uintptr_t>(a.src) % 16) == 0;
+    const int c4 = lane % (kChunk / 4), rv0 = h * (kRowBlock / kIoWaves) + lane / (kChunk / 4);
+    constexpr int kRowsV = kLineThreads / (kChunk / 4);          // 8 rows per float4 instruction
+    constexpr int kInstV = kRowBlock / kIoWaves / kRowsV;         // 2 per lane, plane and block
+    static_assert(kInstV * 4 == kIoInsts, "both forms hold the same values per lane");
+    auto srowv = [&](int t) { return 4u * static_cast<uint32_t>((y0 + rv0 + kRowsV * t) * a.src_pitch); };
+    auto orowv = [&](int t) { return 4u * static_cast<uint32_t>((y0 + rv0 + kRowsV * t) * L); };
+    auto rowv_ok = [&](int t) { return rv0 + kRowsV * t < nrows; };
+    auto ld4 = [&](const float* base, uint32_t off) {
+      return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(base) + off);
+    };
+    auto st4 = [&](float* base, uint32_t off, float4 v) {
+      *reinterpret_cast<float4*>(reinterpret_cast<char*>(base) + off) = v;
+    };
+    auto fast_c = [&](int b) { return vec_ok && causal_i0(b) >= 0 && causal_i0(b) + kChunk <= L; };
+    auto fast_a = [&](int b) { return vec_ok && anti_n(b) == kChunk && anti_lo(b) + kChunk <= L; };
     float fv[kIoInsts], ov[4][kIoInsts];
     // reads of causal block b (f at the block's position q)
     auto read_causal = [&](int b) {
+      if (fast_c(b)) {
+        const uint32_t col = 4u * static_cast<uint32_t>(causal_i0(b) + 4 * c4);
+#pragma unroll
+        for (int t = 0; t < kInstV; ++t) {
+          const float4 v = rowv_ok(t) ? ld4(a.src, srowv(t) + col) : make_float4(0.f, 0.f, 0.f, 0.f);
+          fv[4 * t] = v.x, fv[4 * t + 1] = v.y, fv[4 * t + 2] = v.z, fv[4 * t + 3] = v.w;
+        }
+        return;
+      }
       const int i = causal_i0(b) + q;
       const bool ok = q < min(kChunk, L - causal_i0(b));
       const uint32_t col = 4u * static_cast<uint32_t>(fold(i, L));
@@ -258,6 +291,21 @@ __global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) 
     };
     // reads of anti-causal block b: f and the four causal halves
     auto read_anti = [&](int b) {
+      if (fast_a(b)) {
+        const uint32_t col = 4u * static_cast<uint32_t>(anti_lo(b) + 4 * c4);
+#pragma unroll
+        for (int t = 0; t < kInstV; ++t) {
+          const bool ok = rowv_ok(t);
+          const float4 v = ok ? ld4(a.src, srowv(t) + col) : make_float4(0.f, 0.f, 0.f, 0.f);
+          fv[4 * t] = v.x, fv[4 * t + 1] = v.y, fv[4 * t + 2] = v.z, fv[4 * t + 3] = v.w;
+#pragma unroll
+          for (int p = 0; p < 4; ++p) {
+            const float4 o = ok ? ld4(outk + p * plane, orowv(t) + col) : make_float4(0.f, 0.f, 0.f, 0.f);
+            ov[p][4 * t] = o.x, ov[p][4 * t + 1] = o.y, ov[p][4 * t + 2] = o.z, ov[p][4 * t + 3] = o.w;
+          }
+        }
+        return;
+      }
       const int i = anti_lo(b) + q;
       const bool ok = q < anti_n(b);
       const uint32_t col = 4u * static_cast<uint32_t>(fold(i, L));
@@ -270,7 +318,22 @@ __global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) 
           ov[p][t] = (ok && row_ok(t) && i < L) ? ld_at(outk + p * plane, orow(t) + pos) : 0.f;
       }
     };
-    auto stage = [&](int buf, bool planes) {
+    auto stage = [&](int buf, bool planes, bool fast) {
+      if (fast) {
+#pragma unroll
+        for (int t = 0; t < kInstV; ++t) {
+          const int e0 = (rv0 + kRowsV * t) * kTileStride + 4 * c4;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            ft[buf][e0 + e] = fv[4 * t + e];
+            if (planes) {
+#pragma unroll
+              for (int p = 0; p < 4; ++p) ot[buf][p * kTileFloats + e0 + e] = ov[p][4 * t + e];
+            }
+          }
+        }
+        return;
+      }
 #pragma unroll
       for (int t = 0; t < kIoInsts; ++t) {
         const int r = r0 + kIoRowsPerInst * t;
@@ -286,7 +349,18 @@ __global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) 
     // them out, so that the staging of the next block (which waits for its
     // reads) can come between the two and not wait for these writes
     float sv[4][kIoInsts];
-    auto fetch = [&](int buf) {
+    auto fetch = [&](int buf, bool fast) {
+      if (fast) {
+#pragma unroll
+        for (int t = 0; t < kInstV; ++t) {
+          const int e0 = (rv0 + kRowsV * t) * kTileStride + 4 * c4;
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int p = 0; p < 4; ++p) sv[p][4 * t + e] = ot[buf][p * kTileFloats + e0 + e];
+        }
+        return;
+      }
 #pragma unroll
       for (int t = 0; t < kIoInsts; ++t) {
         const int r = r0 + kIoRowsPerInst * t;
@@ -294,7 +368,19 @@ __global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) 
         for (int p = 0; p < 4; ++p) sv[p][t] = ot[buf][p * kTileFloats + r * kTileStride + q];
       }
     };
-    auto put = [&](int i0, int n) {
+    auto put = [&](int i0, int n, bool fast) {
+      if (fast) {
+        const uint32_t col = 4u * static_cast<uint32_t>(i0 + 4 * c4);
+#pragma unroll
+        for (int t = 0; t < kInstV; ++t) {
+          if (!rowv_ok(t)) continue;
+#pragma unroll
+          for (int p = 0; p < 4; ++p)
+            st4(outk + p * plane, orowv(t) + col,
+                make_float4(sv[p][4 * t], sv[p][4 * t + 1], sv[p][4 * t + 2], sv[p][4 * t + 3]));
+        }
+        return;
+      }
       const int i = i0 + q;
       if (q >= n || i < 0 || i >= L) return;
       const uint32_t pos = 4u * static_cast<uint32_t>(i);
@@ -306,38 +392,38 @@ __global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) 
       }
     };
     read_causal(0);
-    stage(0, false);
+    stage(0, false, fast_c(0));
     if (nb > 1) read_causal(1);
     __syncthreads();
     for (int b = 0; b < nb; ++b) {
-      if (b >= 1) fetch((b - 1) & 1);
+      if (b >= 1) fetch((b - 1) & 1, fast_c(b - 1));
       if (b + 1 < nb) {
-        stage((b + 1) & 1, false);
+        stage((b + 1) & 1, false, fast_c(b + 1));
         if (b + 2 < nb) read_causal(b + 2);
       }
-      if (b >= 1) put(causal_i0(b - 1), min(kChunk, L - causal_i0(b - 1)));
+      if (b >= 1) put(causal_i0(b - 1), min(kChunk, L - causal_i0(b - 1)), fast_c(b - 1));
       __syncthreads();
     }
-    fetch((nb - 1) & 1);
-    put(causal_i0(nb - 1), min(kChunk, L - causal_i0(nb - 1)));
+    fetch((nb - 1) & 1, fast_c(nb - 1));
+    put(causal_i0(nb - 1), min(kChunk, L - causal_i0(nb - 1)), fast_c(nb - 1));
     // the causal halves of every block are in memory before any is read back
     __syncthreads();
     read_anti(0);
-    stage(0, true);
+    stage(0, true, fast_a(0));
     if (nb > 1) read_anti(1);
     __syncthreads();
     for (int b = 0; b < nb; ++b) {
       // (block b + 1 is staged into the buffer block b - 1 leaves: fetched first)
-      if (b >= 1) fetch((b - 1) & 1);
+      if (b >= 1) fetch((b - 1) & 1, fast_a(b - 1));
       if (b + 1 < nb) {
-        stage((b + 1) & 1, true);
+        stage((b + 1) & 1, true, fast_a(b + 1));
         if (b + 2 < nb) read_anti(b + 2);
       }
-      if (b >= 1) put(anti_lo(b - 1), anti_n(b - 1));
+      if (b >= 1) put(anti_lo(b - 1), anti_n(b - 1), fast_a(b - 1));
       __syncthreads();
     }
-    fetch((nb - 1) & 1);
-    put(anti_lo(nb - 1), anti_n(nb - 1));
+    fetch((nb - 1) & 1, fast_a(nb - 1));
+    put(anti_lo(nb - 1), anti_n(nb - 1), fast_a(nb - 1));
     return;
   }
 

@@ -92,6 +92,31 @@ def test_pitched_views_and_repeat_calls_give_the_same_bits():
     assert np.array_equal(outbuf.cpu().numpy(), o1)
 
 
+def test_row_transfers_in_either_form_give_the_same_bits():
+    """Blocks that lie inside a row move between memory and LDS as 16-byte
+    transfers when the row pitch and the image start allow it, float by
+    float otherwise; the same image with an odd pitch, or starting 4 bytes
+    past a 16-byte boundary, gives the bits of the contiguous call."""
+    import torch
+
+    import paper_1603_08081_amd as bfm
+    f = polygon_image(70, 200, 17).astype(np.float32)
+    fit = oracle.fit_kernel("gaussian", 20.0, 255, 1e-3)
+    x = torch.from_numpy(f).cuda()
+    ref, st = bfm.filter_recursive(x, sigma_s=3.0, T=255, d=fit.d, integer_input=True)
+    torch.cuda.synchronize()
+    assert st == 0
+    assert np.abs(ref.cpu().numpy() - R.fourier_recursive(f, 3.0, fit.d, 255)).max() <= TOL
+    for pitch, lead in ((203, 0), (204, 1)):
+        base = torch.zeros((70, pitch), dtype=torch.float32, device="cuda")
+        view = base[:, lead:lead + 200]
+        view.copy_(x)
+        out, st = bfm.filter_recursive(view, sigma_s=3.0, T=255, d=fit.d, integer_input=True)
+        torch.cuda.synchronize()
+        assert st == 0
+        assert torch.equal(out, ref), (pitch, lead)
+
+
 def test_close_to_the_truncated_gaussian_path_at_moderate_sigma():
     # the variant differs from eq. (2)'s truncated kernel by the kernels' difference only
     f = polygon_image(96, 128, 13).astype(np.float32)
