@@ -238,11 +238,12 @@ __global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) 
   auto anti_n = [&](int b) { return L - 1 + M - kChunk * b - anti_lo(b) + 1; };
 
   if (wave >= 4) {
-    // ---- I/O wavefront: rows 32 h + r0 + 4 t, position q of the block
+    // ---- I/O wavefront h: rows r0 + kIoRowsPerInst t (r0 = 16 h + lane / kChunk),
+    // position q of the block, one float per lane and row (the scalar form)
     const int h = wave - 4;
     const int q = lane % kChunk, r0 = h * (kRowBlock / kIoWaves) + lane / kChunk;
-    // byte offsets of row r0 + 4 t in f and in a plane (rows past the image
-    // are never accessed: row_ok masks them)
+    // byte offsets of row r0 + kIoRowsPerInst t in f and in a plane (rows past
+    // the image are never accessed: row_ok masks them)
     const uint32_t s_row0 = 4u * static_cast<uint32_t>((y0 + r0) * a.src_pitch),
                    s_step = 4u * static_cast<uint32_t>(kIoRowsPerInst * a.src_pitch);
     const uint32_t o_row0 = 4u * static_cast<uint32_t>((y0 + r0) * L),
@@ -251,9 +252,10 @@ __global__ void __launch_bounds__(kRowThreads) rec_rows_kernel(const RecArgs a) 
     auto orow = [&](int t) { return o_row0 + static_cast<uint32_t>(t) * o_step; };
     auto row_ok = [&](int t) { return r0 + kIoRowsPerInst * t < nrows; };
     // float4 form of a block that lies inside the row and starts on a
-    // 16-byte boundary: lane = (row rv, quad c4 of 4 positions); this wave
-    // keeps its 16 rows, so a block in either form and the next one in the
-    // other touch the same LDS elements from the same wave
+    // 16-byte boundary: lane = (row rv0 + kRowsV t, quad c4 of 4 positions);
+    // in both forms wavefront h moves the same 16 rows, so a block staged in
+    // one form into the LDS buffer that another block, in the other form,
+    // was just fetched from touches only this wavefront's elements
     const bool vec_ok = (L % 4) == 0 && (a.src_pitch % 4) == 0 &&
                         (reinterpret_cast<uintptr_t>(a.src) % 16) == 0;
     const int c4 = lane % (kChunk / 4), rv0 = h * (kRowBlock / kIoWaves) + lane / (kChunk / 4);
