@@ -1,5 +1,6 @@
-"""Host-side checks of bench.py: the multi-GPU refusal, the flop counts its
-roofline uses, and the lookup of committed HBM counter summaries.  No GPU."""
+"""Host-side checks of bench.py: the multi-GPU refusal, the flop and byte
+counts its rooflines use, and the lookup of committed HBM counter summaries.
+No GPU."""
 import os
 import subprocess
 import sys
@@ -54,3 +55,22 @@ def test_traffic_comes_from_the_committed_summary_only_when_it_matches():
     assert bench.measured_traffic("frames32_2160x3840", "fp16", 8, 144) is None
     assert bench.measured_traffic("frames32_2160x3840", "fp16", 32, 48) is None
     assert bench.measured_traffic("gauss_8192", "fp16", 1, 128) is None
+
+
+@pytest.mark.parametrize("K", [0, 3, 4, 32, 40])
+def test_recursive_traffic_model_uses_the_library_harmonic_groups(K):
+    """bench.py prices the recursive path per harmonic and per group of
+    harmonics; the group count it assumes is the one the library's workspace
+    is laid out for (float32 planes 16 (K + 1) B/px, float64 group shares
+    16 B/px per group)."""
+    import numpy as np
+
+    from paper_1603_08081_amd import native
+    job = native.Job(0x10000000, 0x20000000, spatial="gaussian", sigma_s=24.0, W=0, T=255,
+                     d=np.ones(K + 1), height=64, width=64, integer_input=True)
+    per_px = native.bf_recursive_workspace_bytes(job) // (64 * 64)
+    groups = (per_px - 16 * (K + 1)) // 16
+    assert 16 * (K + 1) + 16 * groups == per_px and groups >= 1
+    assert bench.recursive_bytes_per_px(K) == (K + 1) * (56 + 48) + groups * (48 + 16) + 4
+    if K == 32:
+        assert bench.recursive_bytes_per_px(K) == 4012
