@@ -324,7 +324,8 @@ int bf_dynamic_range(const float* src, int height, int width, int src_pitch, int
  * constant-time smoothing Sec. 2 cites (after eq. (5)): exp(-x^2 / 2 sigma_s^2)
  * fitted by two damped cosine/sine pairs, run as a causal plus an
  * anti-causal fourth-order recursion along rows, then along columns, over a
- * half-sample symmetric extension of about 21 sigma_s + 8 samples, with unit
+ * half-sample symmetric extension of about 16 sigma_s + 8 samples (where the
+ * kernel's tail is below 1e-12 of its peak), with unit
  * sum.  Its run time does not grow with sigma_s beyond that extension; its
  * result differs from bf_filter's truncated Gaussian of eq. (2) by the
  * difference of the two spatial kernels (a variant, not the same filter).

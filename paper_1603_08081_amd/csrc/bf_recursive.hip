@@ -127,10 +127,12 @@ RecCoef recursion_coefficients(double sigma) {
   const double total = (sum_n + sum_a) / sum_d;
   for (int q = 0; q < 4; ++q) c.nc[q] /= total;
   for (int q = 1; q < 5; ++q) c.na[q] /= total;
-  // the slowest decay is e^{-b n / sigma}: beyond this the kernel is < 1e-16 of
-  // its peak; rounded up to whole 32-position blocks so that the row pass's
-  // blocks inside the image start on 16-byte boundaries
-  c.margin = (static_cast<int>(std::ceil(sigma * 16.0 * std::log(10.0) / kFitDecay[1])) + 8 + 31) / 32 * 32;
+  // the slowest decay is e^{-b n / sigma}: beyond this the kernel is < 1e-12 of
+  // its peak (the sum of the tail < 1e-10 of the signal at sigma = 256, far
+  // below the float32 rounding of the planes between the passes); rounded up
+  // to whole 32-position blocks so that the row pass's blocks inside the
+  // image start on 16-byte boundaries
+  c.margin = (static_cast<int>(std::ceil(sigma * 12.0 * std::log(10.0) / kFitDecay[1])) + 8 + 31) / 32 * 32;
   return c;
 }
 
