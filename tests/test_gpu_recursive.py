@@ -29,6 +29,8 @@ def _run(f, **kw):
     (33, 47, 5.5, 30.0, 2),     # extension longer than the image: repeated folding
     (1, 9, 1.0, 15.0, 3),       # a single row
     (64, 1, 1.5, 25.0, 4),      # a single column
+    (33, 48, 5.5, 30.0, 5),     # rows a multiple of 4: 16-byte transfers for the blocks inside a short row
+    (1, 64, 1.0, 15.0, 6),      # a single row in 16-byte transfers
 ])
 def test_matches_the_oracle_on_integer_images(H, Wd, sigma_s, sigma_r, seed):
     f = polygon_image(H, Wd, seed).astype(np.float32)
